@@ -1,0 +1,148 @@
+"""Seeded synthetic workloads for the BCH decoders: random information bits,
+systematic BCH encoding, BPSK over AWGN and channel LLRs (the system model of
+Section II, eq. 1), plus the per-frame random offset d_o that the enhanced
+decoder's cyclic shifts draw (Section III-B).
+
+This module is shared by the product path, the oracle-based tests and the
+benchmark.  It holds none of the decoder's arithmetic.  The code's generator
+polynomial is read from ``codes.json``, which ``make_codes.py`` writes from the
+oracle's code construction.
+
+Randomness: numpy's Philox counter-based generator, keyed by a SeedSequence of
+(seed, code tag, stream, block) so that any block of frames is reproducible on
+its own (a request's frames are the same alone and in a mix).
+Streams: 0 information bits, 1 noise, 2 d_o, 3 mixed-workload draws.
+"""
+from __future__ import annotations
+
+import json
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+# code name -> (m, primitive polynomial, t)
+CODES = {
+    "bch63_36": (6, 0b1000011, 5),
+    "bch63_45": (6, 0b1000011, 3),
+    "bch127_64": (7, 0b10001001, 10),
+    "bch127_78": (7, 0b10001001, 7),
+    "bch127_99": (7, 0b10001001, 4),
+}
+CODE_TAG = {"bch63_36": 1, "bch63_45": 2, "bch127_64": 3, "bch127_78": 4, "bch127_99": 5}
+
+
+@dataclass(frozen=True)
+class CodeSpec:
+    name: str
+    m: int
+    prim: int
+    t: int
+    N: int
+    K: int
+    g: tuple  # generator polynomial coefficients, lowest degree first
+
+    @property
+    def rate(self) -> float:
+        return self.K / self.N
+
+    @property
+    def ld(self) -> int:
+        """Padded row stride of an LLR frame (64 or 128)."""
+        return 64 if self.N <= 64 else 128
+
+    @property
+    def d_p(self) -> int:
+        return 21 if self.N == 63 else 42
+
+
+_specs = None
+
+
+def code(name: str) -> CodeSpec:
+    global _specs
+    if _specs is None:
+        with open(os.path.join(_HERE, "codes.json")) as fh:
+            raw = json.load(fh)
+        _specs = {}
+        for k, v in raw["codes"].items():
+            _specs[k] = CodeSpec(k, v["m"], v["prim"], v["t"], v["N"], v["K"], tuple(v["g"]))
+    return _specs[name]
+
+
+def sigma2_of(ebn0_db, rate):
+    """Noise variance for Eb/N0 in dB at code rate K/N with unit-energy BPSK."""
+    return 1.0 / (2.0 * rate * 10.0 ** (np.asarray(ebn0_db, dtype=np.float64) / 10.0))
+
+
+def _rng(seed: int, tag: int, stream: int, block: int) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(np.random.SeedSequence([seed, tag, stream, block])))
+
+
+def _parity_matrix(spec: CodeSpec) -> np.ndarray:
+    """Row k = remainder of x^(N-K+k) divided by g(x): the parity bits that
+    message bit k contributes to a systematic codeword."""
+    N, K = spec.N, spec.K
+    g = np.array(spec.g, dtype=np.uint8)
+    r = N - K
+    P = np.zeros((K, r), dtype=np.uint8)
+    cur = g[:r].copy()  # x^r mod g, g monic of degree r
+    for k in range(K):
+        P[k] = cur
+        top = cur[r - 1]  # multiply by x, reduce by g
+        cur = np.concatenate([[0], cur[:-1]]).astype(np.uint8)
+        if top:
+            cur ^= g[:r]
+    return P
+
+
+_pmats = {}
+
+
+def encode(spec: CodeSpec, msg: np.ndarray) -> np.ndarray:
+    """Systematic codewords [F][N] (uint8): parity in columns 0..N-K-1, message
+    bits in columns N-K..N-1 (coefficient of x^j in column j)."""
+    if spec.name not in _pmats:
+        _pmats[spec.name] = _parity_matrix(spec).astype(np.float32)
+    P = _pmats[spec.name]
+    par = (msg.astype(np.float32) @ P).astype(np.int64) & 1
+    return np.concatenate([par.astype(np.uint8), msg.astype(np.uint8)], axis=1)
+
+
+@dataclass
+class Frames:
+    llr: np.ndarray        # [F][ld] float32, zero padding beyond N
+    codewords: np.ndarray  # [F][N] uint8, transmitted
+    d_o: np.ndarray        # [F] uint8, random cyclic offset in [0, d_p)
+    ebn0: np.ndarray       # [F] float64
+
+
+def frames(name: str, F: int, ebn0, seed: int, block: int = 0, zero_codeword: bool = False) -> Frames:
+    """F frames of one code.  ebn0 is a scalar or a per-frame array (dB)."""
+    spec = code(name)
+    tag = CODE_TAG[name]
+    N, K, ld = spec.N, spec.K, spec.ld
+    if zero_codeword:
+        msg = np.zeros((F, K), dtype=np.uint8)
+    else:
+        msg = _rng(seed, tag, 0, block).integers(0, 2, size=(F, K), dtype=np.uint8)
+    cw = encode(spec, msg)
+    e = np.broadcast_to(np.asarray(ebn0, dtype=np.float64), (F,)).copy()
+    s2 = sigma2_of(e, spec.rate).astype(np.float32)[:, None]
+    noise = _rng(seed, tag, 1, block).standard_normal(size=(F, N), dtype=np.float32)
+    y = (1.0 - 2.0 * cw.astype(np.float32)) + np.sqrt(s2) * noise
+    llr = np.zeros((F, ld), dtype=np.float32)
+    llr[:, :N] = (2.0 / s2) * y
+    d_o = _rng(seed, tag, 2, block).integers(0, spec.d_p, size=F, dtype=np.uint8)
+    return Frames(llr, cw, d_o, e)
+
+
+def mixed_draws(F: int, seed: int, probs, ebn0_lo: float, ebn0_hi: float, block: int = 0):
+    """Per-frame code index (drawn with the given probabilities) and Eb/N0
+    uniform in [lo, hi], for mixed-code workloads."""
+    r = _rng(seed, 0, 3, block)
+    idx = r.choice(len(probs), size=F, p=np.asarray(probs, dtype=np.float64))
+    e = r.uniform(ebn0_lo, ebn0_hi, size=F)
+    return idx.astype(np.int32), e

@@ -1,0 +1,145 @@
+"""Pins for the oracle's H_o construction (Section III-A, steps 2-6; Table 1)
+and the automorphism block (Section III-B)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+PRIMS = {6: 0b1000011, 7: 0b10001001}
+CODES = {(63, 36): (6, 5), (63, 45): (6, 3), (127, 64): (7, 10), (127, 78): (7, 7),
+         (127, 99): (7, 4)}
+
+
+def code(N, K):
+    m, t = CODES[(N, K)]
+    return oracle.Code(m, PRIMS[m], t)
+
+
+def test_rref_left_to_right_pivots():
+    c = code(63, 45)
+    R = oracle.rref(c.Hstd)
+    assert R.shape == (18, 63)
+    piv = [int(np.argmax(r)) for r in R]
+    assert piv == sorted(piv) and len(set(piv)) == 18
+    for i, p in enumerate(piv):
+        assert R[:, p].sum() == 1 and R[i, p] == 1
+    assert not ((c.G.astype(int) @ R.T.astype(int)) % 2).any()
+
+
+def test_min_density_rows_are_dual_and_lighter():
+    c = code(63, 36)
+    R = oracle.rref(c.Hstd)
+    H1 = oracle.min_density(R, with_shifts=False)
+    assert 0 < H1.shape[0] <= R.shape[0]
+    assert not ((c.G.astype(int) @ H1.T.astype(int)) % 2).any()
+    assert H1.sum(1).max() <= R.sum(1).max()
+    # no two rows in the same cyclic class
+    keys = set()
+    for r in H1:
+        k = min(tuple(np.roll(r, q)) for q in range(63))
+        assert k not in keys
+        keys.add(k)
+
+
+def test_min_density_finds_the_three_weight16_classes_of_63_45():
+    """Table 1 implies M_r1 = 3 for (63,45) (M_o = 33 at beta = 2, 78 at beta = 5);
+    the minimum-weight dual words of (63,45) form exactly three cyclic classes."""
+    c = code(63, 45)
+    H1 = oracle.min_density(oracle.rref(c.Hstd), with_shifts=False)
+    for _ in range(4):
+        H1 = oracle.min_density(H1, with_shifts=True)
+    assert H1.shape[0] == 3 and set(H1.sum(1)) == {16}
+    W = oracle.words_of_weight(c.Hstd, 16)
+    classes = {min(tuple(np.roll(w, q)) for q in range(63)) for w in W}
+    assert len(classes) == 3
+
+
+@pytest.mark.parametrize("NK,beta,target", [((63, 45), 2, 0), ((63, 45), 5, 0),
+                                            ((63, 36), 0, 32), ((127, 99), 0, 33)])
+def test_build_hopt_validity(NK, beta, target):
+    c = code(*NK)
+    H, mr1, seed = oracle.build_hopt(c, beta=beta, target_rows=target, seed=1)
+    M = c.N - c.K
+    want = target if target else mr1 + beta * (M - mr1)
+    assert H.shape == (want, c.N)
+    assert oracle.rank(H) == M
+    assert not ((c.G.astype(int) @ H.T.astype(int)) % 2).any()
+    assert len({tuple(r) for r in H}) == H.shape[0]
+
+
+def test_build_hopt_against_table1_targets():
+    gold = json.load(open(os.path.join(GOLD, "table1_optimized_h.json")))
+    for row in gold["codes"]:
+        if row["N"] == 127 and row["K"] != 99:
+            continue  # covered by the length-127 H_o test in the slow set
+        c = code(row["N"], row["K"])
+        H, mr1, _ = oracle.build_hopt(c, target_rows=row["M_o"], seed=1)
+        s = oracle.pcm_stats(H)
+        assert s["M"] == row["M_o"]
+        lo, hi = row["row_range"]
+        assert s["row_range"][0] >= lo and s["row_range"][1] <= hi
+        # length-4 cycles within 15% of the paper's annealed result
+        assert abs(s["c4"] - row["c4"]) <= 0.15 * row["c4"], (row, s)
+        if (row["N"], row["K"]) == (63, 45):
+            assert mr1 == row["M_r1"]
+
+
+def test_build_hopt_deterministic_in_seed():
+    c = code(63, 45)
+    a = oracle.build_hopt(c, beta=2, seed=7)[0]
+    b = oracle.build_hopt(c, beta=2, seed=7)[0]
+    d = oracle.build_hopt(c, beta=2, seed=8)[0]
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a, d)
+
+
+def test_annealing_lowers_cycles_below_unshifted_padding():
+    c = code(63, 36)
+    H, _, _ = oracle.build_hopt(c, target_rows=122, seed=1)
+    # an unannealed padded matrix repeats rows: its cycle count is far larger
+    H1 = oracle.min_density(oracle.rref(c.Hstd), with_shifts=False)
+    for _ in range(4):
+        H1 = oracle.min_density(H1, with_shifts=True)
+    order = np.argsort(H1.sum(1), kind="stable")
+    pad = np.vstack([H1] + [H1[order[k % len(H1)]][None] for k in range(122 - len(H1))])
+    assert oracle.count_4cycles(H) < 0.5 * oracle.count_4cycles(pad)
+
+
+# ---------------------------------------------------------------- automorphisms
+@pytest.mark.parametrize("N,K", [(63, 36), (63, 45), (127, 99)])
+def test_branch_maps_are_code_automorphisms(N, K):
+    c = code(N, K)
+    dp = 21 if N == 63 else 42
+    for d_o in [0, 1, dp - 1]:
+        maps = oracle.branch_maps(N, 9, d_o)
+        assert maps.shape == (9, N)
+        assert len({tuple(m) for m in maps}) == 9
+        for mp in maps:
+            assert sorted(mp) == list(range(N))
+            Gp = c.G[:, mp]  # every generator row, gathered through the map
+            assert not ((Gp.astype(int) @ c.Hstd.T.astype(int)) % 2).any()
+
+
+def test_branch_map_definitions():
+    N = 63
+    maps = oracle.branch_maps(N, 9, 5)
+    ident, inter, frob = maps[0], maps[1], maps[2]
+    # s = 0: shift d_o = 5 after the type
+    assert list(ident) == [(j - 5) % N for j in range(N)]
+    m0 = oracle.branch_maps(N, 9, 0)
+    # interleaving: even-index bits then odd-index bits
+    assert list(m0[1]) == list(range(0, N, 2)) + list(range(1, N, 2))
+    # Frobenius: bit i moves to position 2i, i.e. the inverse of interleaving
+    y = np.arange(N)
+    moved = np.empty(N, dtype=int)
+    moved[(2 * y) % N] = y
+    assert list(moved) == list(m0[2])
+    assert list(m0[1][m0[2]]) == list(range(N))
+    # s = 1, 2: shifts by d_p + d_o and 2 d_p + d_o
+    assert list(maps[3]) == [(j - 26) % N for j in range(N)]
+    assert list(maps[6]) == [(j - 47) % N for j in range(N)]
+    assert list(oracle.branch_maps(N, 1, 0)[0]) == list(range(N))
