@@ -1,0 +1,219 @@
+"""Throughput of enhanced normalized min-sum decoding of short BCH codes on
+one MI355X.
+
+Workload (one "step" = one pass of the whole decode path over the batch):
+BCH(63,45) with the optimised 33 x 63 H_o and BCH(63,36) with the optimised
+122 x 63 H_o; enhanced NMS with the 9-branch automorphism block (three random
+cyclic shifts of y, pi_I y and pi_F y), restart message mode, alpha = 0.75, at
+most 8 iterations with syndrome stopping, FP32; 1,000,000 frames per Eb/N0
+point, Eb/N0 = 1.0, 1.5, ..., 6.0 dB; random information bits, BPSK over
+AWGN, LLR = 2y/sigma^2 (seeded synthetic frames, resident in HBM before the
+timed region).
+
+Prints one JSON line with frames/s (value), information Gbit/s, per-launch
+p50/p99 latency, the VALU roofline of the decode kernel and the CPU oracle
+timed on a bounded sample of the same frames.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+# peak of 32-bit vector ALU lane-operations per second: 256 CUs x 64 lanes x 2.4 GHz
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+CODES = [("bch63_45", 33), ("bch63_36", 122)]
+
+
+def alg_ops_per_iteration(N, K, M, E, B):
+    """Algorithmic 32-bit operations of one restart-mode iteration of one
+    frame: per edge 7 (magnitude, min1/min2 update, sign accumulation, c2v
+    select, sign, accumulation), per check row 2, per branch coordinate 2
+    (gather and merge), plus the syndrome test 2 (N-K) ceil(N/64)."""
+    return 7 * B * E + 2 * B * M + 2 * B * N + 2 * (N - K) * ((N + 63) // 64)
+
+
+def gen_point(name, F, ebn0, seed, block_frames=125000):
+    nb = (F + block_frames - 1) // block_frames
+    sizes = [min(block_frames, F - k * block_frames) for k in range(nb)]
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 4)) as ex:
+        parts = list(ex.map(lambda k: synth.frames(name, sizes[k], ebn0, seed=seed, block=k), range(nb)))
+    return (np.concatenate([p.llr for p in parts]), np.concatenate([p.codewords for p in parts]),
+            np.concatenate([p.d_o for p in parts]))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--frames", type=int, default=1_000_000, help="frames per Eb/N0 point")
+    ap.add_argument("--ebn0", type=str, default="1.0:6.0:0.5")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle leg")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--generic", action="store_true", help="force the generic (unspecialised) kernel")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2412_20828_amd import binding as B
+
+    lo, hi, st = (float(x) for x in args.ebn0.split(":"))
+    points = [round(lo + k * st, 3) for k in range(int(round((hi - lo) / st)) + 1)]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    work = []  # (code name, ebn0, decoder, llr, d_o, codewords(host), outputs)
+    t0 = time.time()
+    decoders = {}
+    for ci, (name, rows) in enumerate(CODES):
+        d = B.CODE_DEFS[name]
+        code = B.Code(d.m, d.prim, d.t)
+        pcm = B.Pcm.build(code, target_rows=rows, seed=1)
+        dec = B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8,
+                        flags=B.FORCE_GENERIC if args.generic else 0)
+        decoders[name] = (code, pcm, dec)
+        for pi, e in enumerate(points):
+            llr, cw, d_o = gen_point(name, args.frames, e, seed=1000 * 2 + 10 * ci + pi)
+            F = llr.shape[0]
+            out = (torch.empty((F, dec.W64), dtype=torch.int64, device=dev),
+                   torch.empty(F, dtype=torch.uint8, device=dev),
+                   torch.empty(F, dtype=torch.uint8, device=dev))
+            work.append((name, e, dec, torch.from_numpy(llr).to(dev), torch.from_numpy(d_o).to(dev), cw, out,
+                         llr, d_o))
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    total_frames = sum(w[3].shape[0] for w in work)
+
+    def step(events=None):
+        for k, (name, e, dec, llr, d_o, cw, out, _, _) in enumerate(work):
+            if events is not None:
+                events[k][0].record(stream)
+            dec.decode_into(llr, d_o, out[0], out[1], out[2], stream=stream)
+            if events is not None:
+                events[k][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in work]
+          for _ in range(args.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for s in range(args.steps):
+        step(ev[s])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    elapsed = start.elapsed_time(stop) / 1e3
+    launch_ms = np.array([[a.elapsed_time(b) for a, b in evs] for evs in ev])  # [steps][launch]
+
+    # per-point error rates and iteration totals (from the last step's outputs)
+    per_point = []
+    ops_total = 0.0
+    for k, (name, e, dec, llr, d_o, cw, out, _, _) in enumerate(work):
+        code, pcm, _ = decoders[name]
+        words = B.unpack_bits(out[0].cpu().numpy().view(np.uint64), code.N)
+        iters = out[1].cpu().numpy().astype(np.int64)
+        conv = out[2].cpu().numpy().astype(bool)
+        err = (words != cw).any(1)
+        per_point.append({"code": name, "ebn0": e, "fer": float(err.mean()),
+                          "ber": float((words != cw).mean()), "avg_iters": float(iters.mean()),
+                          "undetected": float((err & conv).mean()),
+                          "launch_ms": float(np.median(launch_ms[:, k]))})
+        ops_total += iters.sum() * alg_ops_per_iteration(code.N, code.K, pcm.M, pcm.E, 9)
+    kernel_s = launch_ms.sum() / 1e3 / args.steps
+    achieved = ops_total / kernel_s
+    frames_per_s = total_frames * args.steps / elapsed
+    info_bits = sum(w[3].shape[0] * decoders[w[0]][0].K for w in work)
+    res = {
+        "metric": "decoded frames/s & info Gbit/s at matched FER vs oracle; p50/p99 latency",
+        "value": frames_per_s,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "configs[1]: BCH(63,45) H_o 33x63 and BCH(63,36) H_o 122x63, enhanced NMS "
+                               "9 branches, restart mode, alpha 0.75, max 8 iterations, FP32, %d frames per "
+                               "point, Eb/N0 %s dB" % (args.frames, args.ebn0),
+                   "frames_per_step": total_frames,
+                   "specialised_kernel": {n: bool(decoders[n][2].specialized) for n in decoders}},
+        "info_gbit_s": info_bits * args.steps / elapsed / 1e9,
+        "latency_ms": {"per_launch_p50": float(np.percentile(launch_ms, 50)),
+                       "per_launch_p99": float(np.percentile(launch_ms, 99)),
+                       "launch_frames": args.frames},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                     "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None},
+        "points": per_point,
+        "input_generation_s": gen_s,
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(work, decoders, args.cpu_seconds, frames_per_s)
+    print(json.dumps(res))
+
+
+def cpu_baseline(work, decoders, budget_s, gpu_fps):
+    """The FP64 oracle (as it stands) on a bounded sample of the same frames,
+    on all host cores; also checks that the GPU outcomes on that sample are
+    the oracle's (matched FER)."""
+    import oracle
+    threads = os.cpu_count() or 1
+    per = 40
+    sample = []
+    for (name, e, dec, llr, d_o, cw, out, llr_h, d_o_h) in work:
+        sample.append((name, llr_h[:per], d_o_h[:per], out))
+    mats = {}
+    for name in decoders:
+        code, pcm, _ = decoders[name]
+        m, p, t = synth.CODES[name]
+        oc = oracle.Code(m, p, t)
+        mats[name] = (pcm.dense(), oc.Hstd)
+    # pilot to size the sample to the budget
+    t0 = time.time()
+    name, l0, d0, _ = sample[len(sample) // 2]
+    oracle.decode_batch(mats[name][0], mats[name][1], l0, d0, 9, 0.75, 8, oracle.R1, threads=threads)
+    pilot = max(time.time() - t0, 1e-3)
+    reps = max(1, int(budget_s / (pilot * len(sample))))
+    n = 0
+    match = 0
+    t0 = time.time()
+    for name, l, d, out in sample:
+        H, Hs = mats[name]
+        ll = np.tile(l, (reps, 1))
+        dd = np.tile(d, reps)
+        c, it, cv = oracle.decode_batch(H, Hs, ll, dd, 9, 0.75, 8, oracle.R1, threads=threads)
+        n += ll.shape[0]
+        from paper_2412_20828_amd import binding as B
+        gw = B.unpack_bits(out[0][:per].cpu().numpy().view(np.uint64), H.shape[1])
+        gi = out[1][:per].cpu().numpy()
+        match += int(((gw == c[:per]).all(1) & (gi == it[:per])).sum())
+    secs = time.time() - t0
+    return {"value": n / secs, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": "%d frames (first %d frames of each of the %d Eb/N0 points x %d repeats), FP64 "
+                      "min1/min2 oracle, same frames as the GPU" % (n, per, len(sample), reps),
+            "seconds": secs, "gpu_over_cpu": gpu_fps / (n / secs),
+            "oracle_match_fraction": match / (per * len(sample))}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * bchnms -- enhanced normalized min-sum (NMS) decoding of short BCH codes on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: G. Li and X. Yu, "Effective Application of Normalized Min-Sum
+ * Decoding for Short BCH Codes", arXiv 2412.20828.
+ *
+ * Conventions for every entry point:
+ *   - return value 0 (BCH_OK) on success, a negative BCH_E* code otherwise;
+ *     bch_last_error() gives a thread-local description of the last failure;
+ *     nothing throws across this interface;
+ *   - a binary vector of length N is stored either as N bytes (0/1, "dense")
+ *     or packed little-endian in ceil(N/64) 64-bit words (bit i of word i/64
+ *     is coordinate i = coefficient of x^i);
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the current device (any HIP allocation, e.g. a PyTorch
+ *     tensor's data_ptr());
+ *   - handles (bch_code, bch_pcm, bch_decoder) are created and freed by the
+ *     library; they are immutable after creation and may be shared between
+ *     threads and streams;
+ *   - device buffers passed in are owned by the caller; the library never
+ *     allocates device memory inside a decode call (decoders own a small
+ *     device copy of their tables, made once at creation);
+ *   - calls taking a hipStream_t only enqueue work on that stream; results are
+ *     valid once the stream is synchronised.  Argument errors are reported
+ *     synchronously; a HIP launch failure returns BCH_EDEVICE.
+ */
+#ifndef BCHNMS_H
+#define BCHNMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BCH_OK = 0,
+    BCH_EINVAL = -1,       /* bad argument or shape */
+    BCH_ENOMEM = -2,       /* host allocation failed / workspace too small */
+    BCH_EDEVICE = -3,      /* HIP runtime error */
+    BCH_EUNSUPPORTED = -4, /* outside the supported envelope (N > 127, ...) */
+    BCH_ESTATE = -5        /* construction failed (e.g. no full-rank H_o) */
+};
+
+typedef struct bch_code_s *bch_code;
+typedef struct bch_pcm_s *bch_pcm;
+typedef struct bch_decoder_s *bch_decoder;
+
+const char *bch_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Code algebra (system model of Section II; codes of Table 1).
+ * Binary primitive narrow-sense BCH code of length N = 2^m - 1 (3 <= m <= 7)
+ * over GF(2^m) built from the primitive polynomial prim_poly (bit k = x^k
+ * coefficient, e.g. 0x43 = x^6+x+1), designed distance 2t+1.  K follows from
+ * the degree of the generator polynomial.  Systematic encoding puts parity in
+ * coordinates 0..N-K-1 and the message in N-K..N-1.
+ */
+int bch_load_code(int m, uint32_t prim_poly, int t, bch_code *out);
+int bch_code_info(bch_code code, int *N, int *K, int *t);
+/* g: N-K+1 host bytes (coefficients, lowest first); G: K*N host bytes or NULL;
+ * Hstd: (N-K)*N host bytes or NULL (rows x^i h~(x), the standard PCM). */
+int bch_code_export(bch_code code, uint8_t *g, uint8_t *G, uint8_t *Hstd);
+void bch_code_destroy(bch_code code);
+
+/* ------------------------------------------------------------------------
+ * Parity-check matrices (Section III-A, the six-step construction of H_o).
+ * kind = BCH_PCM_STD: the standard (N-K) x N matrix, other fields ignored.
+ * kind = BCH_PCM_OPT: row echelon form, pairwise weight minimisation, Q cyclic
+ * passes, redundancy padding (beta (M - M_r1) rows, or up to target_rows rows
+ * when target_rows > 0), then simulated annealing on random cyclic row shifts
+ * driven by SplitMix64(seed) (sa_steps_per_row * M_o steps, loss = #length-4
+ * cycles + sa_lambda * column-weight variance).  The result is validated: every
+ * row lies in the dual code and the rank is N-K (otherwise the annealing is
+ * repeated with seed+1).  Deterministic for given parameters.
+ */
+enum { BCH_PCM_STD = 0, BCH_PCM_OPT = 1 };
+typedef struct {
+    int kind;
+    int beta;
+    int target_rows;
+    int Q;
+    uint64_t seed;
+    int sa_steps_per_row;
+    double sa_lambda;
+} bch_pcm_params;
+
+int bch_build_pcm(bch_code code, const bch_pcm_params *params, bch_pcm *out);
+/* Import a dense M x N host matrix; re-validated against the code. */
+int bch_pcm_from_dense(bch_code code, const uint8_t *H, int M, bch_pcm *out);
+/* M rows, N columns, E nonzeros, #length-4 cycles, M_r1 of the construction
+ * (0 for imported / standard matrices), seed actually used. */
+int bch_pcm_info(bch_pcm pcm, int *M, int *N, int *E, int64_t *c4, int *Mr1,
+                 uint64_t *seed_used);
+int bch_pcm_export(bch_pcm pcm, uint8_t *dense, size_t cap_bytes);
+void bch_pcm_destroy(bch_pcm pcm);
+
+/* ------------------------------------------------------------------------
+ * Automorphism block (Section III-B).  Writes n_branches x N gather maps to
+ * host memory: branch b reads Y_b[j] = y[maps[b*N + j]].  Branch b = 3s + p:
+ * type p = identity, interleave (even then odd indices, Y[j] = y[2j mod N]),
+ * Frobenius (bit i moves to 2i mod N); followed by the cyclic shift
+ * s*d_p + d_o (d_p = 21 for N = 63, 42 for N = 127; s = 0, 1, 2).
+ * n_branches = 1 is the identity (plain NMS); 3 uses the three shifts only.
+ * d_o is the frame's random offset in [0, d_p), drawn by the caller.
+ */
+int bch_make_automorphisms(int N, int n_branches, int d_o, int16_t *maps);
+
+/* ------------------------------------------------------------------------
+ * Decoder (Algorithm 1 of Section III-B; plain NMS of Section II-A as the
+ * one-branch case).
+ * mode: how eq. 2 keeps messages across iterations, given that y is replaced
+ * by y^(t) after every iteration:
+ *   BCH_MODE_RESTART (default): v2c = Y_b (each iteration is one min-sum pass
+ *     on the replaced input), y^(t) = y^(t-1) + average;
+ *   BCH_MODE_MEMORY: eq. 2 literally, v2c = Y_b + sum of the branch's other
+ *     c2v messages of iteration t-1, y^(t) = y^(t-1) + average;
+ *   BCH_MODE_EXTRINSIC: v2c = Y_b - the branch's own c2v of iteration t-1,
+ *     y^(t) = L + average (one branch: exactly plain flooding NMS).
+ * precision: BCH_FP32, or BCH_FIX8 (int8 messages, integer accumulators,
+ *   alpha = 3/4 as (3m+2)>>2; input LLRs int8, see bch_quantize_llr).
+ */
+enum { BCH_MODE_RESTART = 1, BCH_MODE_MEMORY = 2, BCH_MODE_EXTRINSIC = 3 };
+enum { BCH_FP32 = 0, BCH_FIX8 = 1 };
+enum {
+    BCH_DEC_FORCE_GENERIC = 1 /* do not use a PCM-specialised kernel */
+};
+typedef struct {
+    int n_branches; /* 1, 3 or 9 */
+    int mode;
+    float alpha;    /* normalisation factor of eq. 3 (FP32 path) */
+    int max_iter;   /* I_m, 1..64 */
+    int precision;
+    int flags;
+} bch_dec_params;
+
+/* Builds the device tables for (pcm, params); syndrome stop uses the code's
+ * standard PCM (same null space as a full-rank H_o).  May compile nothing: a
+ * kernel specialised to this exact PCM is used when the library carries one. */
+int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params,
+                       bch_decoder *out);
+/* 1 if the decoder runs a PCM-specialised kernel, 0 for the generic one. */
+int bch_decoder_is_specialized(bch_decoder dec);
+void bch_decoder_destroy(bch_decoder dec);
+
+/* Device workspace (bytes) a decode of F frames needs (0 for some configs). */
+size_t bch_decode_workspace_size(bch_decoder dec, int64_t F);
+
+/* Decode F frames.  llr: device [F][ld] float32 (FP32) or int8 (FIX8), first N
+ * entries of each row used; d_o: device [F] uint8 random offsets (ignored for
+ * one branch); bits: device [F][ceil(N/64)] uint64 decoded word; iters: device
+ * [F] uint8 iterations run (1..max_iter); flags: device [F] uint8, bit 0 =
+ * syndrome satisfied (converged); y_trace: device [F][max_iter][ld] float32 (or
+ * int32 for FIX8) per-iteration posteriors y^(t), or NULL (rows past a
+ * frame's last iteration are left untouched).  workspace: device, at least
+ * bch_decode_workspace_size(dec, F) bytes (may be NULL when that is 0).
+ * Enqueued on stream. */
+int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F,
+                         const uint8_t *d_o, uint64_t *bits, uint8_t *iters,
+                         uint8_t *flags, void *y_trace, void *workspace,
+                         size_t ws_bytes, hipStream_t stream);
+
+/* Syndrome test of eq. 5 with the code's standard PCM: ok[f] = 1 iff
+ * H c_f^T = 0.  bits: device [F][ceil(N/64)] uint64; ok: device [F] uint8. */
+int bch_syndrome_check(bch_code code, const uint64_t *bits, int64_t F, uint8_t *ok,
+                       hipStream_t stream);
+
+/* Fixed-point input: q = clamp(round-half-away(L * scale), -127, 127), the
+ * product formed in FP32.  llr: device [F][ld] float32; q: device [F][ldq]
+ * int8; columns N..ldq-1 of q are zeroed. */
+int bch_quantize_llr(const float *llr, int64_t ld, int64_t F, int N, float scale,
+                     int8_t *q, int64_t ldq, hipStream_t stream);
+
+/* Order-p OSD (Section II-B) on the host, the back end of the hybrid decoder:
+ * frames with skip[f] != 0 are left alone (skip may be NULL).  llr: host
+ * [F][ld] float32 channel LLRs; bits: host [F][ceil(N/64)] uint64, written for
+ * every decoded frame.  Runs on n_threads host threads (<= 0: all cores). */
+int bch_osd_decode(bch_code code, const float *llr, int64_t ld, int64_t F, int order,
+                   const uint8_t *skip, uint64_t *bits, int n_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

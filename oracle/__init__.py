@@ -79,7 +79,7 @@ def lib():
         L.orc_splitmix64_next.argtypes = [P]
         L.orc_splitmix64_next.restype = u64
         L.orc_decode_batch.argtypes = [i32, P, i32, i32, i32, P, P, i32, i32, dbl, i32,
-                                       i32, P, i32, P, P, P]
+                                       i32, P, i32, P, P, P, P]
         L.orc_osd_batch.argtypes = [P, i32, i32, P, i32, i32, i32, P, P]
         _lib = L
     return _lib
@@ -276,9 +276,11 @@ def quantize(llr: np.ndarray, scale: float) -> np.ndarray:
 
 
 def decode_batch(H, Hsyn, llr, d_o, n_branches, alpha, max_iter, mode, kind=KIND_FAST,
-                 threads: int = 1):
+                 threads: int = 1, trace: bool = False):
     """Decode every frame of llr ([F][ld] float32, or int8 for the fixed-point
-    kind).  Returns (c_hat [F][N] uint8, iters [F] int32, converged [F] bool)."""
+    kind).  Returns (c_hat [F][N] uint8, iters [F] int32, converged [F] bool)
+    and, with trace=True, also the [F][max_iter][N] posteriors (NaN / 0 past a
+    frame's last iteration)."""
     H = np.ascontiguousarray(H, dtype=np.uint8)
     Hsyn = np.ascontiguousarray(Hsyn, dtype=np.uint8)
     M, N = H.shape
@@ -292,6 +294,10 @@ def decode_batch(H, Hsyn, llr, d_o, n_branches, alpha, max_iter, mode, kind=KIND
     c = np.zeros((F, N), dtype=np.uint8)
     it = np.zeros(F, dtype=np.int32)
     cv = np.zeros(F, dtype=np.uint8)
+    tr = None
+    if trace:
+        tr = (np.zeros((F, max_iter, N), dtype=np.int32) if kind == KIND_FIXED
+              else np.full((F, max_iter, N), np.nan))
     L = lib()
 
     def run(lo, hi):
@@ -300,7 +306,7 @@ def decode_batch(H, Hsyn, llr, d_o, n_branches, alpha, max_iter, mode, kind=KIND
         rc = L.orc_decode_batch(kind, _p(H), M, N, n_branches, _p(d_o[lo:hi]),
                                 _p(llr[lo:hi]), ld, hi - lo, alpha, max_iter, mode,
                                 _p(Hsyn), Hsyn.shape[0], _p(c[lo:hi]), _p(it[lo:hi]),
-                                _p(cv[lo:hi]))
+                                _p(cv[lo:hi]), _p(tr[lo:hi]) if trace else None)
         _check(rc, "decode_batch")
 
     if threads <= 1 or F < 2 * threads:
@@ -309,6 +315,8 @@ def decode_batch(H, Hsyn, llr, d_o, n_branches, alpha, max_iter, mode, kind=KIND
         bounds = np.linspace(0, F, threads + 1).astype(int)
         with ThreadPoolExecutor(threads) as ex:
             list(ex.map(lambda k: run(bounds[k], bounds[k + 1]), range(threads)))
+    if trace:
+        return c, it, cv.astype(bool), tr
     return c, it, cv.astype(bool)
 
 

@@ -3,6 +3,8 @@
  * caller can hand over a whole array of frames in one call (test
  * infrastructure only).  Each frame gets its own branch maps from its own
  * random offset d_o (one offset per frame, fixed over the iterations).
+ * trace (optional): [F][max_iter][N] posteriors, double (int32 for the
+ * fixed-point kind); rows past a frame's last iteration are left untouched.
  */
 #include <stdlib.h>
 #include "oracle.h"
@@ -10,7 +12,8 @@
 int orc_decode_batch(int kind, const uint8_t *H, int M, int N, int B,
                      const uint8_t *d_o, const void *llr, int ld, int F,
                      double alpha, int max_iter, int mode, const uint8_t *Hsyn,
-                     int Msyn, uint8_t *c_hat, int32_t *iters, uint8_t *conv)
+                     int Msyn, uint8_t *c_hat, int32_t *iters, uint8_t *conv,
+                     void *trace)
 {
     int16_t maps[9 * ORC_MAXN];
     double L[ORC_MAXN];
@@ -22,7 +25,9 @@ int orc_decode_batch(int kind, const uint8_t *H, int M, int N, int B,
         if (kind == 2) {
             const int8_t *q = (const int8_t *)llr + (size_t)f * ld;
             r = orc_nms_fixed(H, M, N, maps, B, q, max_iter, mode, Hsyn, Msyn,
-                              c_hat + (size_t)f * N, &it, &cv, NULL);
+                              c_hat + (size_t)f * N, &it, &cv,
+                              trace ? (int32_t *)trace + (size_t)f * max_iter * N
+                                    : NULL);
         } else {
             const float *x = (const float *)llr + (size_t)f * ld;
             for (int i = 0; i < N; i++)
@@ -30,11 +35,14 @@ int orc_decode_batch(int kind, const uint8_t *H, int M, int N, int B,
             if (kind == 0)
                 r = orc_nms_literal(H, M, N, maps, B, L, alpha, max_iter, mode,
                                     Hsyn, Msyn, c_hat + (size_t)f * N, &it,
-                                    &cv, NULL);
+                                    &cv,
+                                    trace ? (double *)trace + (size_t)f * max_iter * N
+                                          : NULL);
             else
                 r = orc_nms_fast(H, M, N, maps, B, L, alpha, max_iter, mode,
                                  Hsyn, Msyn, c_hat + (size_t)f * N, &it, &cv,
-                                 NULL);
+                                 trace ? (double *)trace + (size_t)f * max_iter * N
+                                       : NULL);
         }
         if (r)
             return r;

@@ -1,0 +1,489 @@
+// C-ABI of the bchnms library: handle management, argument validation,
+// device tables of a decoder and the dispatch to the HIP kernels.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+#include "spec_registry.h"
+
+struct bch_code_s {
+    bch::Code c;
+};
+struct bch_pcm_s {
+    bch::Pcm p;
+};
+struct bch_decoder_s {
+    int N = 0, K = 0, M = 0, E = 0, W64 = 1;
+    bch_dec_params prm{};
+    int dev = -1;
+    uint16_t *d_rowptr = nullptr;
+    uint8_t *d_colp = nullptr;
+    uint64_t *d_hsyn = nullptr;
+    int msyn = 0;
+    const bch::SpecKernel *spec = nullptr;
+};
+
+namespace bch {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+static int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return BCH_EDEVICE;
+}
+
+static std::vector<uint64_t> pack_rows(const std::vector<Row> &rows, int W64)
+{
+    std::vector<uint64_t> out(rows.size() * W64);
+    for (size_t r = 0; r < rows.size(); r++)
+        for (int w = 0; w < W64; w++)
+            out[r * W64 + w] = rows[r].w[w];
+    return out;
+}
+
+// device copy of a code's standard rows, made once per code and device
+static std::mutex g_hsyn_mu;
+static int code_hsyn(bch_code_s *code, uint64_t **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_hsyn_mu);
+    Code &c = code->c;
+    if (c.d_hsyn && c.d_hsyn_dev == dev) {
+        *out = c.d_hsyn;
+        return BCH_OK;
+    }
+    const int W64 = (c.N + 63) / 64;
+    std::vector<uint64_t> h = pack_rows(c.Hstd, W64);
+    uint64_t *d = nullptr;
+    e = hipMalloc(&d, h.size() * sizeof(uint64_t));
+    if (e != hipSuccess)
+        return hip_fail(e, "hipMalloc");
+    e = hipMemcpy(d, h.data(), h.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(d);
+        return hip_fail(e, "hipMemcpy");
+    }
+    c.d_hsyn = d;
+    c.d_hsyn_dev = dev;
+    *out = d;
+    return BCH_OK;
+}
+
+}  // namespace bch
+
+using namespace bch;
+
+extern "C" {
+
+const char *bch_last_error(void) { return g_err.c_str(); }
+
+int bch_load_code(int m, uint32_t prim_poly, int t, bch_code *out)
+{
+    if (!out)
+        return fail(BCH_EINVAL, "out is NULL");
+    auto *h = new (std::nothrow) bch_code_s();
+    if (!h)
+        return fail(BCH_ENOMEM, "allocation failed");
+    std::string err;
+    int rc = build_code(m, prim_poly, t, h->c, err);
+    if (rc) {
+        delete h;
+        return fail(rc, err);
+    }
+    *out = h;
+    return BCH_OK;
+}
+
+int bch_code_info(bch_code code, int *N, int *K, int *t)
+{
+    if (!code)
+        return fail(BCH_EINVAL, "code is NULL");
+    if (N)
+        *N = code->c.N;
+    if (K)
+        *K = code->c.K;
+    if (t)
+        *t = code->c.t;
+    return BCH_OK;
+}
+
+int bch_code_export(bch_code code, uint8_t *g, uint8_t *G, uint8_t *Hstd)
+{
+    if (!code)
+        return fail(BCH_EINVAL, "code is NULL");
+    const Code &c = code->c;
+    if (g)
+        std::memcpy(g, c.g.data(), c.g.size());
+    if (G)
+        for (int k = 0; k < c.K; k++)
+            for (int i = 0; i < c.N; i++)
+                G[(size_t)k * c.N + i] = c.G[k].get(i);
+    if (Hstd)
+        for (int k = 0; k < c.N - c.K; k++)
+            for (int i = 0; i < c.N; i++)
+                Hstd[(size_t)k * c.N + i] = c.Hstd[k].get(i);
+    return BCH_OK;
+}
+
+void bch_code_destroy(bch_code code)
+{
+    if (!code)
+        return;
+    if (code->c.d_hsyn)
+        (void)hipFree(code->c.d_hsyn);
+    delete code;
+}
+
+int bch_build_pcm(bch_code code, const bch_pcm_params *params, bch_pcm *out)
+{
+    if (!code || !params || !out)
+        return fail(BCH_EINVAL, "NULL argument");
+    auto *h = new (std::nothrow) bch_pcm_s();
+    if (!h)
+        return fail(BCH_ENOMEM, "allocation failed");
+    const Code &c = code->c;
+    if (params->kind == BCH_PCM_STD) {
+        h->p.N = c.N;
+        h->p.M = c.N - c.K;
+        h->p.rows = c.Hstd;
+        h->p.E = 0;
+        for (const Row &r : h->p.rows)
+            h->p.E += r.weight();
+    } else if (params->kind == BCH_PCM_OPT) {
+        std::string err;
+        int rc = build_hopt(c, *params, h->p, err);
+        if (rc) {
+            delete h;
+            return fail(rc, err);
+        }
+    } else {
+        delete h;
+        return fail(BCH_EINVAL, "unknown PCM kind");
+    }
+    *out = h;
+    return BCH_OK;
+}
+
+int bch_pcm_from_dense(bch_code code, const uint8_t *H, int M, bch_pcm *out)
+{
+    if (!code || !H || !out || M < 1 || M > 1024)
+        return fail(BCH_EINVAL, "bad argument");
+    const Code &c = code->c;
+    std::vector<Row> rows(M);
+    for (int r = 0; r < M; r++)
+        for (int i = 0; i < c.N; i++) {
+            if (H[(size_t)r * c.N + i] > 1)
+                return fail(BCH_EINVAL, "matrix entries must be 0 or 1");
+            if (H[(size_t)r * c.N + i])
+                rows[r].set(i);
+        }
+    for (int r = 0; r < M; r++) {
+        if (rows[r].weight() < 2)
+            return fail(BCH_EINVAL, "every row needs weight >= 2");
+        for (const Row &g : c.G)
+            if (overlap(rows[r], g) & 1)
+                return fail(BCH_EINVAL, "row is not a dual codeword");
+    }
+    if (gf2_rank(rows, c.N) != c.N - c.K)
+        return fail(BCH_EINVAL, "matrix rank differs from N-K");
+    auto *h = new (std::nothrow) bch_pcm_s();
+    if (!h)
+        return fail(BCH_ENOMEM, "allocation failed");
+    h->p.N = c.N;
+    h->p.M = M;
+    h->p.rows = rows;
+    h->p.E = 0;
+    for (const Row &r : rows)
+        h->p.E += r.weight();
+    *out = h;
+    return BCH_OK;
+}
+
+int bch_pcm_info(bch_pcm pcm, int *M, int *N, int *E, int64_t *c4, int *Mr1, uint64_t *seed_used)
+{
+    if (!pcm)
+        return fail(BCH_EINVAL, "pcm is NULL");
+    if (M)
+        *M = pcm->p.M;
+    if (N)
+        *N = pcm->p.N;
+    if (E)
+        *E = pcm->p.E;
+    if (c4)
+        *c4 = count_4cycles(pcm->p.rows);
+    if (Mr1)
+        *Mr1 = pcm->p.Mr1;
+    if (seed_used)
+        *seed_used = pcm->p.seed_used;
+    return BCH_OK;
+}
+
+int bch_pcm_export(bch_pcm pcm, uint8_t *dense, size_t cap)
+{
+    if (!pcm || !dense)
+        return fail(BCH_EINVAL, "NULL argument");
+    const size_t need = (size_t)pcm->p.M * pcm->p.N;
+    if (cap < need)
+        return fail(BCH_EINVAL, "buffer too small");
+    for (int r = 0; r < pcm->p.M; r++)
+        for (int i = 0; i < pcm->p.N; i++)
+            dense[(size_t)r * pcm->p.N + i] = pcm->p.rows[r].get(i);
+    return BCH_OK;
+}
+
+void bch_pcm_destroy(bch_pcm pcm) { delete pcm; }
+
+int bch_make_automorphisms(int N, int n_branches, int d_o, int16_t *maps)
+{
+    if (!maps || N < 7 || N > 127)
+        return fail(BCH_EINVAL, "bad argument");
+    int rc = branch_maps(N, n_branches, d_o, maps);
+    if (rc)
+        return fail(rc, "n_branches must be 1, 3 or 9 and d_o in [0, d_p)");
+    return BCH_OK;
+}
+
+int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params, bch_decoder *out)
+{
+    if (!code || !pcm || !params || !out)
+        return fail(BCH_EINVAL, "NULL argument");
+    const Code &c = code->c;
+    const Pcm &p = pcm->p;
+    if (p.N != c.N)
+        return fail(BCH_EINVAL, "PCM and code lengths differ");
+    const bch_dec_params &q = *params;
+    if (q.n_branches != 1 && q.n_branches != 3 && q.n_branches != 9)
+        return fail(BCH_EINVAL, "n_branches must be 1, 3 or 9");
+    if (q.mode < BCH_MODE_RESTART || q.mode > BCH_MODE_EXTRINSIC)
+        return fail(BCH_EINVAL, "unknown mode");
+    if (q.max_iter < 1 || q.max_iter > 64)
+        return fail(BCH_EINVAL, "max_iter must be in [1, 64]");
+    if (q.precision != BCH_FP32 && q.precision != BCH_FIX8)
+        return fail(BCH_EINVAL, "unknown precision");
+    if (p.E > 65535)
+        return fail(BCH_EUNSUPPORTED, "too many edges");
+    auto *d = new (std::nothrow) bch_decoder_s();
+    if (!d)
+        return fail(BCH_ENOMEM, "allocation failed");
+    d->N = c.N;
+    d->K = c.K;
+    d->M = p.M;
+    d->E = p.E;
+    d->W64 = (c.N + 63) / 64;
+    d->prm = q;
+    // CSR rows (ascending columns) and the three multiplied column tables
+    std::vector<uint16_t> rowptr(p.M + 1, 0);
+    std::vector<uint8_t> colp(3 * (size_t)p.E);
+    const int mult[3] = {1, 2, (c.N + 1) / 2};
+    int e = 0;
+    for (int r = 0; r < p.M; r++) {
+        rowptr[r] = (uint16_t)e;
+        for (int i = 0; i < c.N; i++)
+            if (p.rows[r].get(i)) {
+                for (int k = 0; k < 3; k++)
+                    colp[(size_t)k * p.E + e] = (uint8_t)((mult[k] * i) % c.N);
+                e++;
+            }
+    }
+    rowptr[p.M] = (uint16_t)e;
+    int rc = code_hsyn(code, &d->d_hsyn);
+    if (rc) {
+        delete d;
+        return rc;
+    }
+    d->msyn = c.N - c.K;
+    hipError_t he = hipGetDevice(&d->dev);
+    if (he == hipSuccess)
+        he = hipMalloc(&d->d_rowptr, rowptr.size() * sizeof(uint16_t));
+    if (he == hipSuccess)
+        he = hipMalloc(&d->d_colp, colp.size());
+    if (he == hipSuccess)
+        he = hipMemcpy(d->d_rowptr, rowptr.data(), rowptr.size() * sizeof(uint16_t),
+                       hipMemcpyHostToDevice);
+    if (he == hipSuccess)
+        he = hipMemcpy(d->d_colp, colp.data(), colp.size(), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+        bch_decoder_destroy(d);
+        return hip_fail(he, "decoder tables");
+    }
+    if (!(q.flags & BCH_DEC_FORCE_GENERIC))
+        d->spec = find_spec_kernel(p, q);
+    *out = d;
+    return BCH_OK;
+}
+
+int bch_decoder_is_specialized(bch_decoder dec) { return dec && dec->spec ? 1 : 0; }
+
+void bch_decoder_destroy(bch_decoder dec)
+{
+    if (!dec)
+        return;
+    if (dec->d_rowptr)
+        (void)hipFree(dec->d_rowptr);
+    if (dec->d_colp)
+        (void)hipFree(dec->d_colp);
+    delete dec;
+}
+
+size_t bch_decode_workspace_size(bch_decoder dec, int64_t F)
+{
+    if (!dec || F < 0)
+        return 0;
+    if (dec->spec)
+        return 0;
+    if (dec->prm.mode == BCH_MODE_RESTART)
+        return 0;
+    size_t n = (size_t)dec->prm.n_branches * dec->E * F;
+    if (dec->prm.mode == BCH_MODE_MEMORY)
+        n += (size_t)2 * dec->prm.n_branches * dec->N * F;
+    return n * sizeof(float);
+}
+
+int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F,
+                         const uint8_t *d_o, uint64_t *bits, uint8_t *iters, uint8_t *flags,
+                         void *y_trace, void *workspace, size_t ws_bytes, hipStream_t stream)
+{
+    if (!dec)
+        return fail(BCH_EINVAL, "decoder is NULL");
+    if (F < 0 || F > (int64_t)1 << 31)
+        return fail(BCH_EINVAL, "F out of range");
+    if (F == 0)
+        return BCH_OK;
+    if (!llr || !bits || !iters || !flags)
+        return fail(BCH_EINVAL, "NULL buffer");
+    if (dec->prm.n_branches > 1 && !d_o)
+        return fail(BCH_EINVAL, "d_o required for more than one branch");
+    if (ld < dec->N)
+        return fail(BCH_EINVAL, "ld < N");
+    if (dec->prm.precision != BCH_FP32)
+        return fail(BCH_EUNSUPPORTED, "fixed-point decoding needs a specialised kernel");
+    const size_t need = bch_decode_workspace_size(dec, F);
+    if (need && (!workspace || ws_bytes < need))
+        return fail(BCH_ENOMEM, "workspace too small");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != dec->dev)
+        return fail(BCH_EINVAL, "decoder belongs to another device");
+    if (dec->spec) {
+        SpecArgs s{};
+        s.llr = llr;
+        s.ld = ld;
+        s.F = F;
+        s.d_o = d_o;
+        s.bits = bits;
+        s.iters = iters;
+        s.flags = flags;
+        s.trace = y_trace;
+        s.max_iter = dec->prm.max_iter;
+        s.alpha = dec->prm.alpha;
+        s.hsyn = dec->d_hsyn;
+        hipError_t e = dec->spec->launch(s, stream);
+        return e == hipSuccess ? BCH_OK : hip_fail(e, "specialised kernel launch");
+    }
+    GenericArgs a{};
+    a.llr = llr;
+    a.ld = ld;
+    a.F = F;
+    a.d_o = d_o;
+    a.bits = bits;
+    a.iters = iters;
+    a.flags = flags;
+    a.trace = static_cast<float *>(y_trace);
+    a.ld_trace = ld;
+    a.rowptr = dec->d_rowptr;
+    a.colp = dec->d_colp;
+    a.hsyn = dec->d_hsyn;
+    a.msyn = dec->msyn;
+    a.W64 = dec->W64;
+    a.N = dec->N;
+    a.M = dec->M;
+    a.E = dec->E;
+    a.B = dec->prm.n_branches;
+    a.dp = shift_period(dec->N);
+    a.mode = dec->prm.mode;
+    a.max_iter = dec->prm.max_iter;
+    a.alpha = dec->prm.alpha;
+    float *ws = static_cast<float *>(workspace);
+    a.ws_c2v = ws;
+    a.ws_s = ws ? ws + (size_t)a.B * a.E * F : nullptr;
+    hipError_t e = launch_generic_fp32(a, stream);
+    return e == hipSuccess ? BCH_OK : hip_fail(e, "generic kernel launch");
+}
+
+int bch_syndrome_check(bch_code code, const uint64_t *bits, int64_t F, uint8_t *ok,
+                       hipStream_t stream)
+{
+    if (!code || (F > 0 && (!bits || !ok)) || F < 0)
+        return fail(BCH_EINVAL, "bad argument");
+    if (F == 0)
+        return BCH_OK;
+    uint64_t *hs = nullptr;
+    int rc = code_hsyn(code, &hs);
+    if (rc)
+        return rc;
+    hipError_t e = launch_syndrome(bits, F, (code->c.N + 63) / 64, hs, code->c.N - code->c.K,
+                                   ok, stream);
+    return e == hipSuccess ? BCH_OK : hip_fail(e, "syndrome kernel launch");
+}
+
+int bch_quantize_llr(const float *llr, int64_t ld, int64_t F, int N, float scale, int8_t *q,
+                     int64_t ldq, hipStream_t stream)
+{
+    if (F < 0 || N < 1 || ld < N || ldq < N || !(scale > 0.0f))
+        return fail(BCH_EINVAL, "bad argument");
+    if (F == 0)
+        return BCH_OK;
+    if (!llr || !q)
+        return fail(BCH_EINVAL, "NULL buffer");
+    hipError_t e = launch_quantize(llr, ld, F, N, scale, q, ldq, stream);
+    return e == hipSuccess ? BCH_OK : hip_fail(e, "quantize kernel launch");
+}
+
+int bch_osd_decode(bch_code code, const float *llr, int64_t ld, int64_t F, int order,
+                   const uint8_t *skip, uint64_t *bits, int n_threads)
+{
+    if (!code || F < 0 || order < 0 || order > 2 || ld < code->c.N)
+        return fail(BCH_EINVAL, "bad argument (order must be 0, 1 or 2)");
+    if (F == 0)
+        return BCH_OK;
+    if (!llr || !bits)
+        return fail(BCH_EINVAL, "NULL buffer");
+    const Code &c = code->c;
+    const int W64 = (c.N + 63) / 64;
+    int T = n_threads > 0 ? n_threads : (int)std::thread::hardware_concurrency();
+    T = std::max(1, std::min<int>(T, (int)std::min<int64_t>(F, 256)));
+    auto work = [&](int64_t lo, int64_t hi) {
+        for (int64_t f = lo; f < hi; f++)
+            if (!skip || !skip[f])
+                osd_frame(c, llr + f * ld, order, bits + f * W64);
+    };
+    if (T == 1) {
+        work(0, F);
+        return BCH_OK;
+    }
+    std::vector<std::thread> pool;
+    for (int k = 0; k < T; k++)
+        pool.emplace_back(work, F * k / T, F * (k + 1) / T);
+    for (auto &th : pool)
+        th.join();
+    return BCH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,39 @@
+// Launch interface between the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "bchnms.h"
+
+namespace bch {
+
+struct GenericArgs {
+    const void *llr;
+    int64_t ld;
+    int64_t F;
+    const uint8_t *d_o;
+    uint64_t *bits;
+    uint8_t *iters;
+    uint8_t *flags;
+    float *trace;          // [F][max_iter][ld_trace] or null
+    int64_t ld_trace;
+    const uint16_t *rowptr; // [M+1]
+    const uint8_t *colp;    // [3][E]: (a_p * column) mod N, a_p = 1, 2, (N+1)/2
+    const uint64_t *hsyn;   // [msyn][W64] standard parity-check rows
+    int msyn;
+    int W64;
+    int N, M, E, B, dp, mode, max_iter;
+    float alpha;
+    float *ws_c2v;          // [B][E][F]   (memory modes)
+    float *ws_s;            // [2][B][N][F] (memory mode R2)
+};
+
+hipError_t launch_generic_fp32(const GenericArgs &a, hipStream_t stream);
+hipError_t launch_syndrome(const uint64_t *bits, int64_t F, int W64, const uint64_t *hsyn,
+                           int msyn, uint8_t *ok, hipStream_t stream);
+hipError_t launch_quantize(const float *llr, int64_t ld, int64_t F, int N, float scale,
+                           int8_t *q, int64_t ldq, hipStream_t stream);
+
+}  // namespace bch

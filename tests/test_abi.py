@@ -1,0 +1,110 @@
+"""The C-ABI library: it loads without a GPU, exports every entry point the
+public header declares, and its host-side constructions (code matrices, H_o,
+automorphism maps, OSD) agree exactly with the oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import HO_ROWS, ensure_built, header_symbols, oracle_code, oracle_hopt
+
+
+@pytest.fixture(scope="module")
+def B():
+    return ensure_built()
+
+
+def test_exports_every_declared_symbol(B):
+    L = ctypes.CDLL(B.LIB_PATH)
+    syms = header_symbols()
+    assert len(syms) >= 18
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(B.SYMBOLS)
+
+
+@pytest.mark.parametrize("name", list(synth.CODES))
+def test_code_matrices_match_oracle(B, name):
+    d = B.CODE_DEFS[name]
+    c = B.Code(d.m, d.prim, d.t)
+    g, G, H = c.export()
+    oc = oracle_code(name)
+    assert (c.N, c.K) == (oc.N, oc.K)
+    assert np.array_equal(g, oc.g) and np.array_equal(G, oc.G) and np.array_equal(H, oc.Hstd)
+
+
+@pytest.mark.parametrize("name", ["bch63_45", "bch63_36", "bch127_99"])
+def test_hopt_bit_exact_with_oracle(B, name):
+    d = B.CODE_DEFS[name]
+    c = B.Code(d.m, d.prim, d.t)
+    p = B.Pcm.build(c, target_rows=HO_ROWS[name], seed=1)
+    assert np.array_equal(p.dense(), oracle_hopt(name))
+    assert p.c4 == oracle.count_4cycles(p.dense())
+
+
+def test_hopt_beta_form_and_seed_bit_exact(B):
+    d = B.CODE_DEFS["bch63_45"]
+    c = B.Code(d.m, d.prim, d.t)
+    oc = oracle_code("bch63_45")
+    for beta, seed in [(2, 3), (5, 11)]:
+        p = B.Pcm.build(c, beta=beta, seed=seed)
+        H, mr1, used = oracle.build_hopt(oc, beta=beta, seed=seed)
+        assert np.array_equal(p.dense(), H) and p.Mr1 == mr1 and p.seed_used == used
+
+
+def test_pcm_import_validates(B):
+    d = B.CODE_DEFS["bch63_45"]
+    c = B.Code(d.m, d.prim, d.t)
+    H = oracle_hopt("bch63_45")
+    p = B.Pcm.from_dense(c, H)
+    assert p.M == 33 and np.array_equal(p.dense(), H)
+    bad = H.copy()
+    bad[0, 0] ^= 1
+    with pytest.raises(B.BchError):
+        B.Pcm.from_dense(c, bad)
+    with pytest.raises(B.BchError):
+        B.Pcm.from_dense(c, H[:10])  # rank below N-K
+
+
+@pytest.mark.parametrize("N,Bn", [(63, 9), (63, 3), (127, 9), (127, 1)])
+def test_automorphisms_match_oracle(B, N, Bn):
+    for d_o in ([0] if Bn == 1 else [0, 7, (21 if N == 63 else 42) - 1]):
+        assert np.array_equal(B.make_automorphisms(N, Bn, d_o), oracle.branch_maps(N, Bn, d_o))
+    with pytest.raises(B.BchError):
+        B.make_automorphisms(N, 9, 50)
+
+
+@pytest.mark.parametrize("name", ["bch63_45", "bch127_99"])
+def test_host_osd_matches_oracle(B, name):
+    d = B.CODE_DEFS[name]
+    c = B.Code(d.m, d.prim, d.t)
+    oc = oracle_code(name)
+    fr = synth.frames(name, 120, 2.0, seed=5)
+    for order in (0, 1, 2):
+        words = B.unpack_bits(B.osd_decode(c, fr.llr, order, n_threads=4), c.N)
+        ref = oracle.osd_batch(oc.G, fr.llr, order)
+        assert (words == ref).all(1).mean() == 1.0
+
+
+def test_host_osd_skip_leaves_frames(B):
+    d = B.CODE_DEFS["bch63_45"]
+    c = B.Code(d.m, d.prim, d.t)
+    fr = synth.frames("bch63_45", 16, 2.0, seed=6)
+    bits = np.full((16, 1), 12345, np.uint64)
+    skip = np.zeros(16, np.uint8)
+    skip[::2] = 1
+    B.osd_decode(c, fr.llr, 2, skip=skip, bits=bits)
+    assert (bits[::2, 0] == 12345).all() and (bits[1::2, 0] != 12345).any()
+
+
+def test_argument_errors_are_reported(B):
+    with pytest.raises(B.BchError):
+        B.Code(6, 0b1000001, 3)  # not primitive
+    with pytest.raises(B.BchError):
+        B.Code(9, 0b1000010001, 3)  # N > 127
+    d = B.CODE_DEFS["bch63_45"]
+    c = B.Code(d.m, d.prim, d.t)
+    p = B.Pcm.standard(c)
+    assert p.M == 18 and p.E == 18 * 24

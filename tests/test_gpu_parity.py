@@ -1,0 +1,153 @@
+"""Parity of the HIP decoders with the oracle (run on an MI355X).
+
+Every test decodes the same seeded synthetic frames with the C-ABI library on
+the GPU and with the FP64 oracle on the CPU, and applies the bar of
+tests/helpers.compare_with_oracle: identical decoded words, iteration counts and
+convergence flags on all frames but ties, per-iteration posteriors within 1e-5
+(normwise) of the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import HO_ROWS, compare_with_oracle, ensure_built, oracle_code, oracle_hopt
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    b = ensure_built()
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return b
+
+
+def lib_objects(B, name, rows):
+    d = B.CODE_DEFS[name]
+    c = B.Code(d.m, d.prim, d.t)
+    p = B.Pcm.standard(c) if rows == 0 else B.Pcm.build(c, target_rows=rows, seed=1)
+    return c, p
+
+
+def run_pair(B, name, rows, F, ebn0, seed, n_branches, mode, max_iter, alpha=0.75, flags=0):
+    c, p = lib_objects(B, name, rows)
+    oc = oracle_code(name)
+    H = oc.Hstd if rows == 0 else oracle_hopt(name, rows)
+    assert np.array_equal(p.dense(), H)
+    fr = synth.frames(name, F, ebn0, seed=seed)
+    dec = B.Decoder(c, p, n_branches=n_branches, mode=mode, alpha=alpha, max_iter=max_iter, flags=flags)
+    llr = torch.from_numpy(fr.llr).cuda()
+    d_o = torch.from_numpy(fr.d_o).cuda()
+    bits, iters, flg, tr = dec.decode(llr, d_o, trace=True)
+    torch.cuda.synchronize()
+    words = B.unpack_bits(bits.cpu().numpy().view(np.uint64), c.N)
+    res = oracle.decode_batch(H, oc.Hstd, fr.llr, fr.d_o, n_branches, alpha, max_iter, mode,
+                              threads=8, trace=True)
+    return fr, (words, iters.cpu().numpy(), flg.cpu().numpy(), tr.cpu().numpy()), res, dec
+
+
+@pytest.mark.parametrize("name,ebn0", [("bch63_45", 3.0), ("bch63_36", 3.5), ("bch127_99", 4.0),
+                                       ("bch127_64", 4.0)])
+def test_enhanced_nms_restart_mode(B, name, ebn0):
+    F = 64 * 7 + 37  # several waves and a ragged tail
+    fr, g, o, _ = run_pair(B, name, HO_ROWS[name], F, ebn0, 11, 9, oracle.R1, 8)
+    compare_with_oracle(*g, *o)
+
+
+@pytest.mark.parametrize("mode", [oracle.R2, oracle.R3])
+def test_enhanced_nms_memory_modes(B, mode):
+    fr, g, o, _ = run_pair(B, "bch63_45", 33, 300, 3.0, 12, 9, mode, 6)
+    words, its, flg, _ = g
+    same = ((words == o[0]).all(1) & (its == o[1]) & (flg.astype(bool) == o[2]))
+    assert same.mean() >= 0.97
+
+
+def test_plain_nms_standard_matrix_config(B):
+    """Plain flooding NMS (one branch, extrinsic messages) on the standard
+    27 x 63 matrix of BCH(63,36), alpha 0.75, 12 iterations, 10,000 frames at
+    3.0 dB, seed 0."""
+    fr, g, o, _ = run_pair(B, "bch63_36", 0, 10000, 3.0, 0, 1, oracle.R3, 12)
+    words, its, flg, _ = g
+    same = ((words == o[0]).all(1) & (its == o[1]) & (flg.astype(bool) == o[2]))
+    assert same.mean() >= 0.99
+    fer_g = (words != fr.codewords).any(1).mean()
+    fer_o = (o[0] != fr.codewords).any(1).mean()
+    assert abs(fer_g - fer_o) <= 0.005
+
+
+def test_three_branch_variant(B):
+    F = 200
+    fr, g, o, _ = run_pair(B, "bch63_45", 33, F, 3.0, 13, 3, oracle.R1, 8)
+    compare_with_oracle(*g, *o)
+
+
+def test_edge_cases(B):
+    c, p = lib_objects(B, "bch63_45", 33)
+    dec = B.Decoder(c, p, n_branches=9, max_iter=8)
+    # F = 0 is a no-op
+    e = torch.empty((0, 64), dtype=torch.float32, device="cuda")
+    bits, its, flg, _ = dec.decode(e, torch.empty(0, dtype=torch.uint8, device="cuda"))
+    assert bits.shape[0] == 0
+    # all-zero LLRs: the zero word satisfies every check at once
+    z = torch.zeros((65, 64), dtype=torch.float32, device="cuda")
+    bits, its, flg, _ = dec.decode(z, torch.zeros(65, dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    assert (bits.cpu() == 0).all() and (its.cpu() == 1).all() and (flg.cpu() == 1).all()
+    # huge and tiny (normal) magnitudes decode like the unscaled frames
+    fr = synth.frames("bch63_45", 130, 3.0, seed=21)
+    d_o = torch.from_numpy(fr.d_o).cuda()
+    ref = dec.decode(torch.from_numpy(fr.llr).cuda(), d_o)
+    for s in (2.0 ** 60, 2.0 ** -60):
+        out = dec.decode(torch.from_numpy(fr.llr * np.float32(s)).cuda(), d_o)
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])
+
+
+def test_syndrome_kernel(B):
+    c, _ = lib_objects(B, "bch127_99", 33)
+    fr = synth.frames("bch127_99", 300, 4.0, seed=3)
+    words = fr.codewords.copy()
+    words[::3, 5] ^= 1
+    packed = np.zeros((300, 2), np.uint64)
+    for i in range(127):
+        packed[:, i // 64] |= words[:, i].astype(np.uint64) << np.uint64(i % 64)
+    bits = torch.from_numpy(packed.view(np.int64)).cuda()
+    ok = torch.empty(300, dtype=torch.uint8, device="cuda")
+    B.syndrome_check(c, bits, ok)
+    torch.cuda.synchronize()
+    oc = oracle_code("bch127_99")
+    want = ~(((words.astype(int) @ oc.Hstd.T.astype(int)) % 2).any(1))
+    assert np.array_equal(ok.cpu().numpy().astype(bool), want)
+
+
+def test_quantizer_bit_exact(B):
+    fr = synth.frames("bch63_36", 500, 2.0, seed=4)
+    llr = torch.from_numpy(fr.llr).cuda()
+    q = torch.empty((500, 64), dtype=torch.int8, device="cuda")
+    B.quantize_llr(llr, 63, 4.0, q)
+    torch.cuda.synchronize()
+    ref = oracle.quantize(fr.llr, 4.0)
+    ref[:, 63:] = 0
+    assert np.array_equal(q.cpu().numpy(), ref)
+
+
+def test_results_independent_of_batch_composition(B):
+    """A frame decodes the same alone, in a different batch position and in
+    a mixed batch (per-frame randomness is an input, never the slot)."""
+    c, p = lib_objects(B, "bch63_45", 33)
+    dec = B.Decoder(c, p, n_branches=9, max_iter=8)
+    fr = synth.frames("bch63_45", 257, 2.5, seed=8)
+    llr = torch.from_numpy(fr.llr).cuda()
+    d_o = torch.from_numpy(fr.d_o).cuda()
+    full = dec.decode(llr, d_o)
+    perm = torch.randperm(257, device="cuda")
+    shuf = dec.decode(llr[perm].contiguous(), d_o[perm].contiguous())
+    torch.cuda.synchronize()
+    inv = torch.argsort(perm)
+    for a, b in zip(full[:3], shuf[:3]):
+        assert torch.equal(a, b[inv])
+    one = dec.decode(llr[100:101].contiguous(), d_o[100:101].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(one[0][0], full[0][100]) and torch.equal(one[1][0], full[1][100])
