@@ -36,11 +36,11 @@ CODES = [("bch63_45", 33), ("bch63_36", 122)]
 
 
 def alg_ops_per_iteration(N, K, M, E, B):
-    """Algorithmic 32-bit operations of one restart-mode iteration of one
-    frame: per edge 7 (magnitude, min1/min2 update, sign accumulation, c2v
-    select, sign, accumulation), per check row 2, per branch coordinate 2
-    (gather and merge), plus the syndrome test 2 (N-K) ceil(N/64)."""
-    return 7 * B * E + 2 * B * M + 2 * B * N + 2 * (N - K) * ((N + 63) // 64)
+    """Algorithmic 32-bit operations of one iteration of one frame: per edge 8
+    (v2c 1, min1/min2/argmin 3, sign 1, c2v select and sign 2, bit-sum add 1),
+    per check row 2, per branch coordinate 2 (permutation and merge), plus the
+    syndrome test 2 (N-K) ceil(N/64)."""
+    return 8 * B * E + 2 * B * M + 2 * B * N + 2 * (N - K) * ((N + 63) // 64)
 
 
 def gen_point(name, F, ebn0, seed, block_frames=125000):
@@ -77,7 +77,7 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
 
-    work = []  # (code name, ebn0, decoder, llr, d_o, codewords(host), outputs)
+    work = []  # (code name, ebn0, decoder, llr, d_o, codewords(host), outputs, host llr, host d_o, workspace)
     t0 = time.time()
     decoders = {}
     for ci, (name, rows) in enumerate(CODES):
@@ -92,7 +92,8 @@ def main():
             F = llr.shape[0]
             out = (torch.empty((F, dec.W64), dtype=torch.int64, device=dev),
                    torch.empty(F, dtype=torch.uint8, device=dev),
-                   torch.empty(F, dtype=torch.uint8, device=dev))
+                   torch.empty(F, dtype=torch.uint8, device=dev),
+                   torch.empty(max(1, dec.workspace_size(F)), dtype=torch.uint8, device=dev))
             work.append((name, e, dec, torch.from_numpy(llr).to(dev), torch.from_numpy(d_o).to(dev), cw, out,
                          llr, d_o))
     torch.cuda.synchronize()
@@ -103,7 +104,7 @@ def main():
         for k, (name, e, dec, llr, d_o, cw, out, _, _) in enumerate(work):
             if events is not None:
                 events[k][0].record(stream)
-            dec.decode_into(llr, d_o, out[0], out[1], out[2], stream=stream)
+            dec.decode_into(llr, d_o, out[0], out[1], out[2], workspace=out[3], stream=stream)
             if events is not None:
                 events[k][1].record(stream)
 
@@ -177,8 +178,8 @@ def cpu_baseline(work, decoders, budget_s, gpu_fps):
     on all host cores; also checks that the GPU outcomes on that sample are
     the oracle's (matched FER)."""
     import oracle
-    threads = os.cpu_count() or 1
-    per = 40
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    per = 64
     sample = []
     for (name, e, dec, llr, d_o, cw, out, llr_h, d_o_h) in work:
         sample.append((name, llr_h[:per], d_o_h[:per], out))
@@ -188,12 +189,12 @@ def cpu_baseline(work, decoders, budget_s, gpu_fps):
         m, p, t = synth.CODES[name]
         oc = oracle.Code(m, p, t)
         mats[name] = (pcm.dense(), oc.Hstd)
-    # pilot to size the sample to the budget
+    # pilot (all points once) to size the sample to the budget
     t0 = time.time()
-    name, l0, d0, _ = sample[len(sample) // 2]
-    oracle.decode_batch(mats[name][0], mats[name][1], l0, d0, 9, 0.75, 8, oracle.R1, threads=threads)
+    for name, l0, d0, _ in sample:
+        oracle.decode_batch(mats[name][0], mats[name][1], l0, d0, 9, 0.75, 8, oracle.R1, threads=threads)
     pilot = max(time.time() - t0, 1e-3)
-    reps = max(1, int(budget_s / (pilot * len(sample))))
+    reps = max(1, int(budget_s / pilot))
     n = 0
     match = 0
     t0 = time.time()

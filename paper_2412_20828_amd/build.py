@@ -28,7 +28,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
 HOST_SRCS = ["host_code.cpp", "host_pcm.cpp", "host_osd.cpp", "capi.cpp", "spec_registry.cpp"]
-HIP_SRCS = ["k_generic.hip"]
+HIP_SRCS = ["k_generic.hip", "k_bucket.hip"]
 
 CXXFLAGS = ["-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",
             "-D__HIP_PLATFORM_AMD__", "-I" + INCLUDE, "-I" + CSRC, "-I" + os.path.join(ROCM, "include")]
@@ -56,9 +56,10 @@ def _compile_host(src, extra_inc=None):
     return out
 
 
-def _compile_hip(src):
+def _compile_hip(src, extra_inc=None):
     out = _obj(src)
-    _run([os.path.join(ROCM, "bin", "hipcc")] + HIPFLAGS + ["-c", src, "-o", out])
+    inc = ["-I" + extra_inc] if extra_inc else []
+    _run([os.path.join(ROCM, "bin", "hipcc")] + HIPFLAGS + inc + ["-c", src, "-o", out])
     return out
 
 
@@ -82,7 +83,7 @@ def build(verbose: bool = True, with_spec: bool = True) -> str:
     os.makedirs(gen_dir, exist_ok=True)
     # stage 1: empty specialisation table
     _write_if_changed(os.path.join(gen_dir, "spec_table.inc"),
-                      "static const SpecKernel kSpecKernels[] = {{0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n")
+                      "static const SpecKernel kSpecKernels[] = {{0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n")
     jobs = [(_compile_host, os.path.join(CSRC, s), gen_dir) for s in HOST_SRCS]
     with cf.ThreadPoolExecutor(max_workers=8) as ex:
         futs = [ex.submit(fn, src, inc) for fn, src, inc in jobs]
@@ -100,7 +101,7 @@ def build(verbose: bool = True, with_spec: bool = True) -> str:
     _write_if_changed(os.path.join(gen_dir, "spec_table.inc"), table)
     with cf.ThreadPoolExecutor(max_workers=8) as ex:
         futs = [ex.submit(_compile_host, os.path.join(CSRC, "spec_registry.cpp"), gen_dir)]
-        futs += [ex.submit(_compile_hip, s) for s in spec_srcs]
+        futs += [ex.submit(_compile_hip, s, gen_dir) for s in spec_srcs]
         new = [f.result() for f in futs]
     objs = [o for o in objs if not o.endswith("spec_registry.cpp.o")] + new
     _link(objs, LIB)

@@ -26,6 +26,8 @@ struct bch_decoder_s {
     uint8_t *d_colp = nullptr;
     uint64_t *d_hsyn = nullptr;
     int msyn = 0;
+    int n_cu = 0;
+    int range_frames = 256;
     const bch::SpecKernel *spec = nullptr;
 };
 
@@ -326,6 +328,9 @@ int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params,
     }
     if (!(q.flags & BCH_DEC_FORCE_GENERIC))
         d->spec = find_spec_kernel(p, q);
+    if (hipDeviceGetAttribute(&d->n_cu, hipDeviceAttributeMultiprocessorCount, d->dev) != hipSuccess ||
+        d->n_cu <= 0)
+        d->n_cu = 256;
     *out = d;
     return BCH_OK;
 }
@@ -347,8 +352,12 @@ size_t bch_decode_workspace_size(bch_decoder dec, int64_t F)
 {
     if (!dec || F < 0)
         return 0;
-    if (dec->spec)
-        return 0;
+    if (dec->spec) {
+        size_t n = bucket_ws_bytes(F, shift_period(dec->N), dec->range_frames);
+        if (dec->spec->y_global)
+            n += (size_t)dec->n_cu * dec->spec->waves_per_cu * dec->N * 64 * sizeof(float) + 256;
+        return n;
+    }
     if (dec->prm.mode == BCH_MODE_RESTART)
         return 0;
     size_t n = (size_t)dec->prm.n_branches * dec->E * F;
@@ -382,19 +391,30 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
     if (hipGetDevice(&cur) != hipSuccess || cur != dec->dev)
         return fail(BCH_EINVAL, "decoder belongs to another device");
     if (dec->spec) {
-        SpecArgs s{};
-        s.llr = llr;
+        const int dp = shift_period(dec->N);
+        BucketWs w = bucket_ws_carve(workspace, F, dp, dec->range_frames);
+        hipError_t e = launch_bucketing(d_o, F, dp, dec->prm.n_branches > 1, dec->range_frames, w, stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "bucketing prepass");
+        SpecLaunch s{};
+        s.llr = static_cast<const float *>(llr);
         s.ld = ld;
-        s.F = F;
-        s.d_o = d_o;
+        s.order = w.order;
+        s.ranges = w.ranges;
+        s.n_ranges = w.n_ranges;
+        s.range_counter = w.range_counter;
         s.bits = bits;
         s.iters = iters;
         s.flags = flags;
-        s.trace = y_trace;
+        s.trace = static_cast<float *>(y_trace);
+        s.yscratch = nullptr;
+        if (dec->spec->y_global) {
+            uintptr_t p = reinterpret_cast<uintptr_t>(workspace) + bucket_ws_bytes(F, dp, dec->range_frames);
+            s.yscratch = reinterpret_cast<float *>((p + 255) & ~(uintptr_t)255);
+        }
         s.max_iter = dec->prm.max_iter;
         s.alpha = dec->prm.alpha;
-        s.hsyn = dec->d_hsyn;
-        hipError_t e = dec->spec->launch(s, stream);
+        e = dec->spec->launch(s, dec->n_cu, stream);
         return e == hipSuccess ? BCH_OK : hip_fail(e, "specialised kernel launch");
     }
     GenericArgs a{};

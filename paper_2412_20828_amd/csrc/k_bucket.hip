@@ -1,0 +1,170 @@
+// Bucketing prepass of the specialised decoder: frames are grouped by their
+// random cyclic offset d_o so that a wave's 64 frames share every branch
+// permutation.  Counting sort without global atomics:
+//   1. each block of BLK frames counts its frames per bucket;
+//   2. one workgroup scans the per-block counts bucket by bucket (bucket
+//      starts, per-block offsets) and cuts every bucket into ranges of at most
+//      range_frames frames;
+//   3. each block places its frames at its offsets plus their rank inside the
+//      block (LDS counters).
+// Frames keep their input order inside a (block, bucket) up to the LDS-atomic
+// ranks; no result depends on that order (every frame is decoded on its own).
+#include <hip/hip_runtime.h>
+
+#include "spec_launch.h"
+
+namespace bch {
+
+namespace {
+
+constexpr int MAXB = 64;
+constexpr int BLK = 2048;   // frames per counting block
+constexpr int TPB = 256;    // threads per counting block
+constexpr int SCAN = 1024;  // threads of the scan workgroup
+
+__device__ __forceinline__ int bucket_of(const uint8_t *d_o, int64_t f, int dp, int use)
+{
+    return use ? (int)d_o[f] % dp : 0;
+}
+
+__global__ void __launch_bounds__(TPB) bucket_count(const uint8_t *__restrict__ d_o, int64_t F, int dp,
+                                                    int use, int *__restrict__ blk_hist)
+{
+    __shared__ int h[MAXB];
+    if (threadIdx.x < MAXB)
+        h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * BLK;
+    for (int k = threadIdx.x; k < BLK; k += TPB) {
+        const int64_t f = base + k;
+        if (f < F)
+            atomicAdd(&h[bucket_of(d_o, f, dp, use)], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < dp)
+        blk_hist[(size_t)blockIdx.x * dp + threadIdx.x] = h[threadIdx.x];
+}
+
+// one workgroup: per-block offsets in bucket-major order, bucket starts, ranges
+__global__ void __launch_bounds__(SCAN) bucket_scan(int *__restrict__ blk_hist, int nblk, int dp,
+                                                    int range_frames, BucketWs w)
+{
+    __shared__ int part[SCAN];
+    __shared__ int bucket_total[MAXB];
+    __shared__ int bucket_start[MAXB];
+    __shared__ int range_start[MAXB + 1];
+    const int tid = threadIdx.x;
+    // each thread owns a contiguous chunk of blocks
+    const int per = (nblk + SCAN - 1) / SCAN;
+    const int lo = tid * per, hi = min(nblk, lo + per);
+    for (int d = 0; d < dp; d++) {
+        int s = 0;
+        for (int b = lo; b < hi; b++)
+            s += blk_hist[(size_t)b * dp + d];
+        part[tid] = s;
+        __syncthreads();
+        for (int off = 1; off < SCAN; off <<= 1) {  // inclusive scan
+            const int v = tid >= off ? part[tid - off] : 0;
+            __syncthreads();
+            part[tid] += v;
+            __syncthreads();
+        }
+        int run = part[tid] - s;  // exclusive prefix of this thread's chunk
+        for (int b = lo; b < hi; b++) {
+            const int c = blk_hist[(size_t)b * dp + d];
+            blk_hist[(size_t)b * dp + d] = run;  // offset inside the bucket
+            run += c;
+        }
+        if (tid == SCAN - 1)
+            bucket_total[d] = part[tid];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int start = 0, nr = 0;
+        for (int d = 0; d < dp; d++) {
+            bucket_start[d] = start;
+            range_start[d] = nr;
+            start += bucket_total[d];
+            nr += (bucket_total[d] + range_frames - 1) / range_frames;
+        }
+        range_start[dp] = nr;
+        *w.n_ranges = nr;
+        *w.range_counter = 0;
+    }
+    __syncthreads();
+    if (tid < dp) {
+        w.counts[tid] = bucket_total[tid];
+        w.cursor[tid] = bucket_start[tid];
+    }
+    for (int d = 0; d < dp; d++) {
+        const int nr = range_start[d + 1] - range_start[d];
+        for (int r = tid; r < nr; r += SCAN) {
+            const int o = r * range_frames;
+            const int e = min(o + range_frames, bucket_total[d]);
+            w.ranges[range_start[d] + r] = make_int4(bucket_start[d] + o, bucket_start[d] + e, d, 0);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(TPB) bucket_place(const uint8_t *__restrict__ d_o, int64_t F, int dp,
+                                                    int use, const int *__restrict__ blk_off, BucketWs w)
+{
+    __shared__ int h[MAXB];
+    if (threadIdx.x < MAXB)
+        h[threadIdx.x] = threadIdx.x < dp ? w.cursor[threadIdx.x] + blk_off[(size_t)blockIdx.x * dp + threadIdx.x] : 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * BLK;
+    for (int k = threadIdx.x; k < BLK; k += TPB) {
+        const int64_t f = base + k;
+        if (f < F) {
+            const int pos = atomicAdd(&h[bucket_of(d_o, f, dp, use)], 1);
+            w.order[pos] = (int)f;
+        }
+    }
+}
+
+size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+int64_t n_blocks(int64_t F) { return (F + BLK - 1) / BLK; }
+
+}  // namespace
+
+size_t bucket_ws_bytes(int64_t F, int dp, int range_frames)
+{
+    const size_t head = align16(sizeof(int) * (2 * (size_t)dp + 2));
+    const size_t nr = (size_t)(F / range_frames) + dp + 1;
+    const size_t hist = align16(sizeof(int) * (size_t)n_blocks(F) * dp);
+    return head + nr * sizeof(int4) + hist + align16((size_t)F * sizeof(int));
+}
+
+BucketWs bucket_ws_carve(void *ws, int64_t F, int dp, int range_frames)
+{
+    BucketWs w;
+    char *p = static_cast<char *>(ws);
+    int *h = reinterpret_cast<int *>(p);
+    w.counts = h;
+    w.cursor = h + dp;
+    w.n_ranges = h + 2 * dp;
+    w.range_counter = h + 2 * dp + 1;
+    p += align16(sizeof(int) * (2 * (size_t)dp + 2));
+    w.ranges = reinterpret_cast<int4 *>(p);
+    p += ((size_t)(F / range_frames) + dp + 1) * sizeof(int4);
+    w.blk_hist = reinterpret_cast<int *>(p);
+    p += align16(sizeof(int) * (size_t)n_blocks(F) * dp);
+    w.order = reinterpret_cast<int *>(p);
+    return w;
+}
+
+hipError_t launch_bucketing(const uint8_t *d_o, int64_t F, int dp, int use_offsets, int range_frames,
+                            const BucketWs &w, hipStream_t stream)
+{
+    if (dp > MAXB || F <= 0)
+        return hipErrorInvalidValue;
+    const int nblk = (int)n_blocks(F);
+    hipLaunchKernelGGL(bucket_count, dim3(nblk), dim3(TPB), 0, stream, d_o, F, dp, use_offsets, w.blk_hist);
+    hipLaunchKernelGGL(bucket_scan, dim3(1), dim3(SCAN), 0, stream, w.blk_hist, nblk, dp, range_frames, w);
+    hipLaunchKernelGGL(bucket_place, dim3(nblk), dim3(TPB), 0, stream, d_o, F, dp, use_offsets, w.blk_hist, w);
+    return hipGetLastError();
+}
+
+}  // namespace bch

@@ -1,0 +1,44 @@
+// Launch arguments of the PCM-specialised decode kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bch {
+
+struct SpecLaunch {
+    const float *llr;      // device [F][ld]
+    int64_t ld;
+    const int *order;      // frame indices grouped by d_o (bucketing prepass)
+    const int4 *ranges;    // {start, end, d_o, 0} slices of order
+    const int *n_ranges;
+    int *range_counter;    // next range to hand out (zeroed by the prepass)
+    uint64_t *bits;        // [F][W64]
+    uint8_t *iters;        // [F]
+    uint8_t *flags;        // [F]
+    float *trace;          // [F][max_iter][ld] or null
+    float *yscratch;       // [grid][N][64] when the kernel keeps y in device memory
+    int max_iter;
+    float alpha;
+};
+
+// Bucketing prepass: groups frames by random offset d_o (reduced modulo d_p;
+// all in bucket 0 for one branch) and cuts every bucket into ranges of at
+// most range_frames frames.
+struct BucketWs {
+    int *counts;
+    int *cursor;
+    int *n_ranges;
+    int *range_counter;
+    int4 *ranges;
+    int *blk_hist;  // [blocks of 2048 frames][d_p] counts, then offsets
+    int *order;
+};
+
+size_t bucket_ws_bytes(int64_t F, int dp, int range_frames);
+BucketWs bucket_ws_carve(void *ws, int64_t F, int dp, int range_frames);
+hipError_t launch_bucketing(const uint8_t *d_o, int64_t F, int dp, int use_offsets, int range_frames,
+                            const BucketWs &w, hipStream_t stream);
+
+}  // namespace bch

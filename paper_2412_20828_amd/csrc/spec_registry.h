@@ -9,28 +9,17 @@
 #include <cstdint>
 
 #include "internal.h"
+#include "spec_launch.h"
 
 namespace bch {
-
-struct SpecArgs {
-    const void *llr;
-    int64_t ld;
-    int64_t F;
-    const uint8_t *d_o;
-    uint64_t *bits;
-    uint8_t *iters;
-    uint8_t *flags;
-    void *trace;
-    int max_iter;
-    float alpha;
-    const uint64_t *hsyn;
-};
 
 struct SpecKernel {
     uint64_t fingerprint;  // of the matrix rows, see pcm_fingerprint()
     int N, M, B, mode, precision;
+    int waves_per_cu;  // persistent grid = CUs x waves_per_cu wavefronts
+    int y_global;      // 1: y lives in device scratch [grid][N][64] floats
     const char *name;
-    hipError_t (*launch)(const SpecArgs &, hipStream_t);
+    hipError_t (*launch)(const SpecLaunch &, int n_cu, hipStream_t);
 };
 
 uint64_t pcm_fingerprint(const Pcm &p);

@@ -1,15 +1,171 @@
 """Generator of PCM-specialised decode kernels (stage 2 of the build).
 
-For every matrix the library is built for, the stage-1 library constructs the
-matrix (the construction is deterministic), and a HIP kernel is emitted with
-the matrix compiled in.  Returns the generated sources and the lookup table.
+The stage-1 library constructs each matrix the library is built for (the
+construction is deterministic); this module then emits, per matrix, the row
+function of nms_spec_fp32.inc with the matrix compiled in (static register
+indices for every edge) and the syndrome test with the code's standard rows
+as constants, plus the lookup table that maps a matrix fingerprint to the
+kernel.
 """
 from __future__ import annotations
 
-# (code name, target rows of H_o or 0 for the standard matrix, n_branches, mode)
-SPECS: list = []
+import ctypes
+import os
+
+import numpy as np
+
+# (code name, target rows of H_o, n_branches, mode, waves per CU of the persistent grid)
+SPECS = [
+    ("bch63_45", 33, 9, 1, 5),
+    ("bch63_36", 122, 9, 1, 4),
+    ("bch63_36", 32, 9, 1, 5),
+    ("bch127_99", 33, 9, 1, 4),
+    ("bch127_64", 72, 9, 1, 4),
+    ("bch127_78", 57, 9, 1, 4),
+]
+CODE_DEFS = {
+    "bch63_36": (6, 0b1000011, 5),
+    "bch63_45": (6, 0b1000011, 3),
+    "bch127_64": (7, 0b10001001, 10),
+    "bch127_78": (7, 0b10001001, 7),
+    "bch127_99": (7, 0b10001001, 4),
+}
+
+
+class _PcmParams(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("beta", ctypes.c_int), ("target_rows", ctypes.c_int),
+                ("Q", ctypes.c_int), ("seed", ctypes.c_uint64), ("sa_steps_per_row", ctypes.c_int),
+                ("sa_lambda", ctypes.c_double)]
+
+
+def _matrices(lib, name, rows):
+    m, prim, t = CODE_DEFS[name]
+    code = ctypes.c_void_p()
+    assert lib.bch_load_code(m, prim, t, ctypes.byref(code)) == 0
+    N, K = ctypes.c_int(), ctypes.c_int()
+    lib.bch_code_info(code, ctypes.byref(N), ctypes.byref(K), None)
+    N, K = N.value, K.value
+    Hs = np.zeros((N - K, N), np.uint8)
+    lib.bch_code_export(code, None, None, Hs.ctypes.data_as(ctypes.c_void_p))
+    p = _PcmParams(1, 2, rows, 4, 1, 200, 10.0)
+    pcm = ctypes.c_void_p()
+    assert lib.bch_build_pcm(code, ctypes.byref(p), ctypes.byref(pcm)) == 0
+    M = ctypes.c_int()
+    lib.bch_pcm_info(pcm, ctypes.byref(M), None, None, None, None, None)
+    H = np.zeros((M.value, N), np.uint8)
+    lib.bch_pcm_export(pcm, H.ctypes.data_as(ctypes.c_void_p), H.size)
+    lib.bch_pcm_destroy(pcm)
+    lib.bch_code_destroy(code)
+    return H, Hs
+
+
+def fingerprint(H: np.ndarray) -> int:
+    """FNV-1a over N, M and the rows packed as two little-endian 64-bit words
+    (the library's pcm_fingerprint)."""
+    M, N = H.shape
+    h = 1469598103934665603
+    mask = (1 << 64) - 1
+
+    def mix(v):
+        nonlocal h
+        for k in range(8):
+            h ^= (v >> (8 * k)) & 0xFF
+            h = (h * 1099511628211) & mask
+
+    mix(N)
+    mix(M)
+    for r in H:
+        w0 = sum(1 << i for i in range(min(N, 64)) if r[i])
+        w1 = sum(1 << (i - 64) for i in range(64, N) if r[i])
+        mix(w0)
+        mix(w1)
+    return h
+
+
+def body_source(H: np.ndarray) -> str:
+    M, N = H.shape
+    W32 = (N + 31) // 32
+    out = ["__device__ __forceinline__ void body(const float *__restrict__ A, "
+           "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
+    touched = [False] * N
+    for j in range(M):
+        cols = [int(c) for c in np.nonzero(H[j])[0]]
+        masks = [0] * W32
+        for c in cols:
+            masks[c // 32] |= 1 << (c % 32)
+        cnt = " + ".join("__builtin_popcount(S[%d] & 0x%08xu)" % (k, masks[k]) for k in range(W32) if masks[k])
+        out.append("    { // row %d" % j)
+        out.append("        const uint32_t cnt = %s;" % cnt)
+        out.append("        const float sg = __uint_as_float(0x3f800000u | (cnt << 31));")
+        c0, c1 = cols[0], cols[1]
+        out.append("        float m1 = fminf(A[%d], A[%d]), m2 = fmaxf(A[%d], A[%d]);" % (c0, c1, c0, c1))
+        for c in cols[2:]:
+            out.append("        m2 = __builtin_amdgcn_fmed3f(m1, m2, A[%d]); m1 = fminf(m1, A[%d]);" % (c, c))
+        out.append("        const float P = m1 + m2;")
+        for c in cols:
+            mag = "__builtin_amdgcn_fmed3f(m1, m2, P - A[%d])" % c
+            if touched[c]:
+                out.append("        T[%d] = __builtin_fmaf(sg, %s, T[%d]);" % (c, mag, c))
+            else:
+                out.append("        T[%d] = sg * %s;" % (c, mag))
+                touched[c] = True
+        out.append("    }")
+    for c in range(N):
+        if not touched[c]:
+            out.append("    T[%d] = 0.0f;" % c)
+    out.append("}")
+    return "\n".join(out)
+
+
+def syndrome_source(Hs: np.ndarray) -> str:
+    Ms, N = Hs.shape
+    W64 = (N + 63) // 64
+    out = ["__device__ __forceinline__ bool syndrome_zero(const uint64_t *w)", "{", "    uint32_t odd = 0;"]
+    for r in range(Ms):
+        terms = []
+        for k in range(W64):
+            mask = sum(1 << (i - 64 * k) for i in range(64 * k, min(N, 64 * k + 64)) if Hs[r, i])
+            if mask:
+                terms.append("__popcll(w[%d] & 0x%016xull)" % (k, mask))
+        out.append("    odd |= %s;" % " + ".join(terms))
+    out += ["    return (odd & 1u) == 0;", "}"]
+    return "\n".join(out)
 
 
 def generate(stage1_lib: str, out_dir: str):
-    table = "static const SpecKernel kSpecKernels[] = {{0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n"
-    return [], table
+    lib = ctypes.CDLL(stage1_lib)
+    P = ctypes.c_void_p
+    lib.bch_load_code.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, P]
+    lib.bch_code_info.argtypes = [P, P, P, P]
+    lib.bch_code_export.argtypes = [P, P, P, P]
+    lib.bch_build_pcm.argtypes = [P, ctypes.POINTER(_PcmParams), P]
+    lib.bch_pcm_info.argtypes = [P, P, P, P, P, P, P]
+    lib.bch_pcm_export.argtypes = [P, P, ctypes.c_size_t]
+    lib.bch_pcm_destroy.argtypes = [P]
+    lib.bch_code_destroy.argtypes = [P]
+    srcs = []
+    entries = []
+    decls = []
+    for (name, rows, B, mode, waves) in SPECS:
+        H, Hs = _matrices(lib, name, rows)
+        M, N = H.shape
+        ns = "spec_%s_m%d_b%d" % (name, M, B)
+        body_path = os.path.join(out_dir, ns + "_body.inc")
+        with open(body_path, "w") as fh:
+            fh.write("// generated: %s, H_o %d x %d, %d edges\n" % (name, M, N, int(H.sum())))
+            fh.write(body_source(H) + "\n\n" + syndrome_source(Hs) + "\n")
+        src_path = os.path.join(out_dir, ns + ".hip")
+        with open(src_path, "w") as fh:
+            fh.write('#include "spec_launch.h"\n')
+            yg = 1 if N > 64 else 0
+            fh.write("#define SPEC_N %d\n#define SPEC_B %d\n#define SPEC_NS %s\n#define SPEC_WAVES %d\n"
+                     "#define SPEC_Y_GLOBAL %d\n" % (N, B, ns, waves, yg))
+            fh.write('#define SPEC_BODY "%s"\n' % os.path.basename(body_path))
+            fh.write('#include "nms_spec_fp32.inc"\n')
+        srcs.append(src_path)
+        decls.append("namespace %s { hipError_t launch(const SpecLaunch &, int, hipStream_t); }" % ns)
+        entries.append("    {0x%016xull, %d, %d, %d, %d, 0, %d, %d, \"%s\", &%s::launch}," %
+                       (fingerprint(H), N, M, B, mode, waves, 1 if N > 64 else 0, ns, ns))
+    table = "\n".join(decls) + "\nstatic const SpecKernel kSpecKernels[] = {\n" + "\n".join(entries) + \
+        "\n    {0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n"
+    return srcs, table

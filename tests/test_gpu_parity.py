@@ -48,12 +48,57 @@ def run_pair(B, name, rows, F, ebn0, seed, n_branches, mode, max_iter, alpha=0.7
     return fr, (words, iters.cpu().numpy(), flg.cpu().numpy(), tr.cpu().numpy()), res, dec
 
 
+@pytest.mark.parametrize("generic", [False, True])
 @pytest.mark.parametrize("name,ebn0", [("bch63_45", 3.0), ("bch63_36", 3.5), ("bch127_99", 4.0),
-                                       ("bch127_64", 4.0)])
-def test_enhanced_nms_restart_mode(B, name, ebn0):
+                                       ("bch127_64", 4.0), ("bch127_78", 4.0)])
+def test_enhanced_nms_restart_mode(B, name, ebn0, generic):
     F = 64 * 7 + 37  # several waves and a ragged tail
-    fr, g, o, _ = run_pair(B, name, HO_ROWS[name], F, ebn0, 11, 9, oracle.R1, 8)
+    fr, g, o, dec = run_pair(B, name, HO_ROWS[name], F, ebn0, 11, 9, oracle.R1, 8,
+                             flags=B.FORCE_GENERIC if generic else 0)
+    assert dec.specialized == (not generic)
     compare_with_oracle(*g, *o)
+
+
+@pytest.mark.parametrize("F", [1, 2, 63, 64, 65, 300])
+def test_specialised_small_and_ragged_batches(B, F):
+    fr, g, o, dec = run_pair(B, "bch63_45", 33, F, 2.0, 30 + F, 9, oracle.R1, 8)
+    assert dec.specialized
+    compare_with_oracle(*g, *o)
+
+
+@pytest.mark.parametrize("name,rows,F,ebn0", [("bch63_45", 33, 1_000_000, 3.0),
+                                              ("bch63_36", 122, 1_000_000, 3.5),
+                                              ("bch127_64", 72, 4_000_000, 4.0)])
+def test_full_size_batches_sampled(B, name, rows, F, ebn0):
+    """Batch sizes of the paper-sized workloads (1,000,000 frames per point for
+    the length-63 codes, 4,000,000 for length 127) in the benchmark's launch
+    configuration; the oracle decodes a random sample of frames one by one and
+    every converged frame's word must satisfy the syndrome test."""
+    c, p = lib_objects(B, name, rows)
+    oc = oracle_code(name)
+    H = oracle_hopt(name, rows)
+    dec = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8)
+    assert dec.specialized
+    blocks = 8
+    per = F // blocks
+    parts = [synth.frames(name, per, ebn0, seed=77, block=k) for k in range(blocks)]
+    llr = torch.from_numpy(np.concatenate([q.llr for q in parts])).cuda()
+    d_o = torch.from_numpy(np.concatenate([q.d_o for q in parts])).cuda()
+    bits, iters, flg, _ = dec.decode(llr, d_o)
+    ok = torch.empty(F, dtype=torch.uint8, device="cuda")
+    B.syndrome_check(c, bits, ok)
+    torch.cuda.synchronize()
+    flg_h = flg.cpu().numpy()
+    assert np.array_equal(ok.cpu().numpy()[flg_h == 1], np.ones(int(flg_h.sum()), np.uint8))
+    it_h = iters.cpu().numpy()
+    assert it_h.min() >= 1 and it_h.max() <= 8 and (it_h[flg_h == 0] == 8).all()
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(F, 1500, replace=False))
+    llr_h = llr[torch.from_numpy(idx).cuda()].cpu().numpy()
+    d_h = d_o.cpu().numpy()[idx]
+    res = oracle.decode_batch(H, oc.Hstd, llr_h, d_h, 9, 0.75, 8, oracle.R1, threads=8, trace=True)
+    words = B.unpack_bits(bits.cpu().numpy().view(np.uint64)[idx], c.N)
+    compare_with_oracle(words, it_h[idx], flg_h[idx], None, *res)
 
 
 @pytest.mark.parametrize("mode", [oracle.R2, oracle.R3])
