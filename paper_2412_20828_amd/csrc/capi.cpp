@@ -382,8 +382,8 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
         return fail(BCH_EINVAL, "d_o required for more than one branch");
     if (ld < dec->N)
         return fail(BCH_EINVAL, "ld < N");
-    if (dec->prm.precision != BCH_FP32)
-        return fail(BCH_EUNSUPPORTED, "fixed-point decoding needs a specialised kernel");
+    if (dec->prm.precision != BCH_FP32 && !dec->spec)
+        return fail(BCH_EUNSUPPORTED, "fixed-point decoding needs a kernel specialised to this matrix");
     const size_t need = bch_decode_workspace_size(dec, F);
     if (need && (!workspace || ws_bytes < need))
         return fail(BCH_ENOMEM, "workspace too small");
@@ -397,7 +397,7 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
         if (e != hipSuccess)
             return hip_fail(e, "bucketing prepass");
         SpecLaunch s{};
-        s.llr = static_cast<const float *>(llr);
+        s.llr = llr;
         s.ld = ld;
         s.order = w.order;
         s.ranges = w.ranges;
@@ -406,7 +406,7 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
         s.bits = bits;
         s.iters = iters;
         s.flags = flags;
-        s.trace = static_cast<float *>(y_trace);
+        s.trace = y_trace;
         s.yscratch = nullptr;
         if (dec->spec->y_global) {
             uintptr_t p = reinterpret_cast<uintptr_t>(workspace) + bucket_ws_bytes(F, dp, dec->range_frames);

@@ -8,7 +8,7 @@
 namespace bch {
 
 struct SpecLaunch {
-    const float *llr;      // device [F][ld]
+    const void *llr;       // device [F][ld] float32 (FP32) or int8 (FIX8)
     int64_t ld;
     const int *order;      // frame indices grouped by d_o (bucketing prepass)
     const int4 *ranges;    // {start, end, d_o, 0} slices of order
@@ -17,7 +17,7 @@ struct SpecLaunch {
     uint64_t *bits;        // [F][W64]
     uint8_t *iters;        // [F]
     uint8_t *flags;        // [F]
-    float *trace;          // [F][max_iter][ld] or null
+    void *trace;           // [F][max_iter][ld] float32 / int32, or null
     float *yscratch;       // [grid][N][64] when the kernel keeps y in device memory
     int max_iter;
     float alpha;

@@ -14,14 +14,19 @@ import os
 
 import numpy as np
 
-# (code name, target rows of H_o, n_branches, mode, waves per CU of the persistent grid)
+# (code name, target rows of H_o, n_branches, mode, precision (0 FP32, 1 FIX8),
+#  waves per CU of the persistent grid)
 SPECS = [
-    ("bch63_45", 33, 9, 1, 5),
-    ("bch63_36", 122, 9, 1, 4),
-    ("bch63_36", 32, 9, 1, 5),
-    ("bch127_99", 33, 9, 1, 4),
-    ("bch127_64", 72, 9, 1, 4),
-    ("bch127_78", 57, 9, 1, 4),
+    ("bch63_45", 33, 9, 1, 0, 5),
+    ("bch63_36", 122, 9, 1, 0, 4),
+    ("bch63_36", 32, 9, 1, 0, 5),
+    ("bch127_99", 33, 9, 1, 0, 4),
+    ("bch127_64", 72, 9, 1, 0, 4),
+    ("bch127_78", 57, 9, 1, 0, 4),
+    ("bch63_45", 33, 9, 1, 1, 5),
+    ("bch63_36", 122, 9, 1, 1, 4),
+    ("bch127_99", 33, 9, 1, 1, 4),
+    ("bch127_64", 72, 9, 1, 1, 4),
 ]
 CODE_DEFS = {
     "bch63_36": (6, 0b1000011, 5),
@@ -117,6 +122,50 @@ def body_source(H: np.ndarray) -> str:
     return "\n".join(out)
 
 
+def body_source_fix8(H: np.ndarray) -> str:
+    """Row function of the fixed-point decoder.  A holds the int8-saturated
+    magnitudes (integers 0..127 held exactly as floats).  The c2v magnitude is
+    (3m + 2) >> 2 = floor(0.75 m + 0.5) of the row's other-entry minimum m;
+    with c1, c2 those of min1, min2 and K = c2 + 128 min1, med3(c1, c2,
+    K - 128 A) is c2 at the argmin (A = min1) and c1 at every other entry
+    (A >= min1 + 1 gives a third argument below 0).  All values are small
+    integers, so every step is exact."""
+    M, N = H.shape
+    W32 = (N + 31) // 32
+    out = ["__device__ __forceinline__ void body(const float *__restrict__ A, "
+           "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
+    touched = [False] * N
+    for j in range(M):
+        cols = [int(c) for c in np.nonzero(H[j])[0]]
+        masks = [0] * W32
+        for c in cols:
+            masks[c // 32] |= 1 << (c % 32)
+        cnt = " + ".join("__builtin_popcount(S[%d] & 0x%08xu)" % (k, masks[k]) for k in range(W32) if masks[k])
+        out.append("    { // row %d" % j)
+        out.append("        const uint32_t cnt = %s;" % cnt)
+        out.append("        const float sg = __uint_as_float(0x3f800000u | (cnt << 31));")
+        c0, c1 = cols[0], cols[1]
+        out.append("        float m1 = fminf(A[%d], A[%d]), m2 = fmaxf(A[%d], A[%d]);" % (c0, c1, c0, c1))
+        for c in cols[2:]:
+            out.append("        m2 = __builtin_amdgcn_fmed3f(m1, m2, A[%d]); m1 = fminf(m1, A[%d]);" % (c, c))
+        out.append("        const float q1 = floorf(__builtin_fmaf(m1, 0.75f, 0.5f)), "
+                   "q2 = floorf(__builtin_fmaf(m2, 0.75f, 0.5f));")
+        out.append("        const float K = __builtin_fmaf(m1, 128.0f, q2);")
+        for c in cols:
+            mag = "__builtin_amdgcn_fmed3f(q1, q2, __builtin_fmaf(A[%d], -128.0f, K))" % c
+            if touched[c]:
+                out.append("        T[%d] = __builtin_fmaf(sg, %s, T[%d]);" % (c, mag, c))
+            else:
+                out.append("        T[%d] = sg * %s;" % (c, mag))
+                touched[c] = True
+        out.append("    }")
+    for c in range(N):
+        if not touched[c]:
+            out.append("    T[%d] = 0.0f;" % c)
+    out.append("}")
+    return "\n".join(out)
+
+
 def syndrome_source(Hs: np.ndarray) -> str:
     Ms, N = Hs.shape
     W64 = (N + 63) // 64
@@ -146,26 +195,29 @@ def generate(stage1_lib: str, out_dir: str):
     srcs = []
     entries = []
     decls = []
-    for (name, rows, B, mode, waves) in SPECS:
-        H, Hs = _matrices(lib, name, rows)
+    mats = {}
+    for (name, rows, B, mode, prec, waves) in SPECS:
+        if (name, rows) not in mats:
+            mats[(name, rows)] = _matrices(lib, name, rows)
+        H, Hs = mats[(name, rows)]
         M, N = H.shape
-        ns = "spec_%s_m%d_b%d" % (name, M, B)
+        ns = "spec_%s_m%d_b%d%s" % (name, M, B, "_fix8" if prec else "")
         body_path = os.path.join(out_dir, ns + "_body.inc")
         with open(body_path, "w") as fh:
             fh.write("// generated: %s, H_o %d x %d, %d edges\n" % (name, M, N, int(H.sum())))
-            fh.write(body_source(H) + "\n\n" + syndrome_source(Hs) + "\n")
+            fh.write((body_source_fix8(H) if prec else body_source(H)) + "\n\n" + syndrome_source(Hs) + "\n")
         src_path = os.path.join(out_dir, ns + ".hip")
         with open(src_path, "w") as fh:
             fh.write('#include "spec_launch.h"\n')
             yg = 1 if N > 64 else 0
             fh.write("#define SPEC_N %d\n#define SPEC_B %d\n#define SPEC_NS %s\n#define SPEC_WAVES %d\n"
-                     "#define SPEC_Y_GLOBAL %d\n" % (N, B, ns, waves, yg))
+                     "#define SPEC_Y_GLOBAL %d\n#define SPEC_FIX8 %d\n" % (N, B, ns, waves, yg, prec))
             fh.write('#define SPEC_BODY "%s"\n' % os.path.basename(body_path))
             fh.write('#include "nms_spec_fp32.inc"\n')
         srcs.append(src_path)
         decls.append("namespace %s { hipError_t launch(const SpecLaunch &, int, hipStream_t); }" % ns)
-        entries.append("    {0x%016xull, %d, %d, %d, %d, 0, %d, %d, \"%s\", &%s::launch}," %
-                       (fingerprint(H), N, M, B, mode, waves, 1 if N > 64 else 0, ns, ns))
+        entries.append("    {0x%016xull, %d, %d, %d, %d, %d, %d, %d, \"%s\", &%s::launch}," %
+                       (fingerprint(H), N, M, B, mode, prec, waves, 1 if N > 64 else 0, ns, ns))
     table = "\n".join(decls) + "\nstatic const SpecKernel kSpecKernels[] = {\n" + "\n".join(entries) + \
         "\n    {0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n"
     return srcs, table

@@ -196,3 +196,75 @@ def test_results_independent_of_batch_composition(B):
     one = dec.decode(llr[100:101].contiguous(), d_o[100:101].contiguous())
     torch.cuda.synchronize()
     assert torch.equal(one[0][0], full[0][100]) and torch.equal(one[1][0], full[1][100])
+
+
+# ------------------------------------------------------------ fixed point
+def run_fix8_pair(B, name, rows, F, ebn0, seed, scale=4.0):
+    c, p = lib_objects(B, name, rows)
+    oc = oracle_code(name)
+    H = oracle_hopt(name, rows)
+    fr = synth.frames(name, F, ebn0, seed=seed)
+    llr = torch.from_numpy(fr.llr).cuda()
+    q = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
+    B.quantize_llr(llr, c.N, scale, q)
+    dec = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, max_iter=8, precision=B.FIX8)
+    assert dec.specialized
+    d_o = torch.from_numpy(fr.d_o).cuda()
+    bits, iters, flg, tr = dec.decode(q, d_o, trace=True)
+    torch.cuda.synchronize()
+    qh = q.cpu().numpy()
+    words = B.unpack_bits(bits.cpu().numpy().view(np.uint64), c.N)
+    oc_, oit, ocv, otr = oracle.decode_batch(H, oc.Hstd, qh, fr.d_o, 9, 0.75, 8, oracle.R1,
+                                             kind=oracle.KIND_FIXED, threads=8, trace=True)
+    return fr, words, iters.cpu().numpy(), flg.cpu().numpy(), tr.cpu().numpy(), oc_, oit, ocv, otr
+
+
+@pytest.mark.parametrize("name,ebn0", [("bch63_45", 3.0), ("bch63_36", 3.5), ("bch127_99", 4.0),
+                                       ("bch127_64", 3.5)])
+def test_fixed_point_bit_exact(B, name, ebn0):
+    """int8 messages, (3m+2)>>2 c2v magnitudes, integer branch average:
+    identical decoded words, iteration counts, flags and every per-iteration
+    posterior as the integer oracle, on every frame."""
+    F = 64 * 5 + 17
+    fr, w, it, fl, tr, ow, oit, ocv, otr = run_fix8_pair(B, name, HO_ROWS[name], F, ebn0, 41)
+    assert np.array_equal(w, ow)
+    assert np.array_equal(it, oit)
+    assert np.array_equal(fl.astype(bool), ocv)
+    N = w.shape[1]
+    for f in range(F):
+        assert np.array_equal(tr[f, :oit[f], :N], otr[f, :oit[f]]), f
+
+
+@pytest.mark.parametrize("name,rows", [("bch127_64", 72), ("bch127_99", 33)])
+def test_fixed_point_full_size_sampled(B, name, rows):
+    """4,000,000 frames per point in one launch; 1000 sampled frames checked
+    bit-exactly against the integer oracle."""
+    c, p = lib_objects(B, name, rows)
+    oc = oracle_code(name)
+    H = oracle_hopt(name, rows)
+    F = 4_000_000
+    parts = [synth.frames(name, F // 8, 3.0, seed=91, block=k) for k in range(8)]
+    llr = torch.from_numpy(np.concatenate([q.llr for q in parts])).cuda()
+    d_o_h = np.concatenate([q.d_o for q in parts])
+    q = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
+    B.quantize_llr(llr, c.N, 4.0, q)
+    del llr
+    dec = B.Decoder(c, p, n_branches=9, max_iter=8, precision=B.FIX8)
+    bits, iters, flg, _ = dec.decode(q, torch.from_numpy(d_o_h).cuda())
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(3).choice(F, 1000, replace=False))
+    qh = q[torch.from_numpy(idx).cuda()].cpu().numpy()
+    ow, oit, ocv = oracle.decode_batch(H, oc.Hstd, qh, d_o_h[idx], 9, 0.75, 8, oracle.R1,
+                                       kind=oracle.KIND_FIXED, threads=8)
+    words = B.unpack_bits(bits.cpu().numpy().view(np.uint64)[idx], c.N)
+    assert np.array_equal(words, ow)
+    assert np.array_equal(iters.cpu().numpy()[idx], oit)
+    assert np.array_equal(flg.cpu().numpy()[idx].astype(bool), ocv)
+
+
+def test_fixed_point_without_kernel_is_rejected(B):
+    c, p = lib_objects(B, "bch63_45", 0)  # standard matrix: no fixed-point kernel
+    dec = B.Decoder(c, p, n_branches=1, mode=B.MODE_EXTRINSIC, max_iter=4, precision=B.FIX8)
+    q = torch.zeros((64, 64), dtype=torch.int8, device="cuda")
+    with pytest.raises(B.BchError):
+        dec.decode(q)
