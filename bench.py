@@ -32,7 +32,17 @@ import synth  # noqa: E402
 
 # peak of 32-bit vector ALU lane-operations per second: 256 CUs x 64 lanes x 2.4 GHz
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
-CODES = [("bch63_45", 33), ("bch63_36", 122)]
+WORKLOADS = {
+    # name: (codes with H_o rows, Eb/N0 grid, frames per point, precisions, description)
+    "sweep63": ([("bch63_45", 33), ("bch63_36", 122)], "1.0:6.0:0.5", 1_000_000, ["fp32"],
+                "configs[1]: BCH(63,45) H_o 33x63 and BCH(63,36) H_o 122x63, enhanced NMS 9 branches, restart "
+                "mode, alpha 0.75, max 8 iterations, FP32"),
+    "fix127": ([("bch127_64", 72), ("bch127_99", 33)], "2.0:5.0:0.5", 4_000_000, ["fp32", "fix8"],
+               "configs[2]: BCH(127,64) H_o 72x127 and BCH(127,99) H_o 33x127, enhanced NMS 9 branches, restart "
+               "mode, max 8 iterations, FP32 (alpha 0.75) vs int8 messages (alpha 3/4 shift-add, LLR x 4 "
+               "quantised)"),
+}
+FIX_SCALE = 4.0
 
 
 def alg_ops_per_iteration(N, K, M, E, B):
@@ -57,9 +67,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--frames", type=int, default=1_000_000, help="frames per Eb/N0 point")
-    ap.add_argument("--ebn0", type=str, default="1.0:6.0:0.5")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle leg")
+    ap.add_argument("--workload", default="sweep63", choices=sorted(WORKLOADS))
+    ap.add_argument("--frames", type=int, default=0, help="frames per Eb/N0 point (0: the workload's)")
+    ap.add_argument("--ebn0", type=str, default="", help="lo:hi:step dB (empty: the workload's)")
+    ap.add_argument("--cpu-seconds", type=float, default=30.0, help="budget of the CPU oracle leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--generic", action="store_true", help="force the generic (unspecialised) kernel")
     args = ap.parse_args()
@@ -71,37 +82,54 @@ def main():
 
     from paper_2412_20828_amd import binding as B
 
+    codes, grid, frames, precisions, wdesc = WORKLOADS[args.workload]
+    args.frames = args.frames or frames
+    args.ebn0 = args.ebn0 or grid
     lo, hi, st = (float(x) for x in args.ebn0.split(":"))
     points = [round(lo + k * st, 3) for k in range(int(round((hi - lo) / st)) + 1)]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
 
-    work = []  # (code name, ebn0, decoder, llr, d_o, codewords(host), outputs, host llr, host d_o, workspace)
+    # work items: (code name, ebn0, decoder, device input, d_o, codewords, outputs, host llr, host d_o, precision)
+    work = []
     t0 = time.time()
     decoders = {}
-    for ci, (name, rows) in enumerate(CODES):
+    seed_base = {"sweep63": 2000, "fix127": 3000}[args.workload]
+    for ci, (name, rows) in enumerate(codes):
         d = B.CODE_DEFS[name]
         code = B.Code(d.m, d.prim, d.t)
         pcm = B.Pcm.build(code, target_rows=rows, seed=1)
-        dec = B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8,
-                        flags=B.FORCE_GENERIC if args.generic else 0)
-        decoders[name] = (code, pcm, dec)
+        decs = {}
+        for prec in precisions:
+            decs[prec] = B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8,
+                                   precision=B.FIX8 if prec == "fix8" else B.FP32,
+                                   flags=B.FORCE_GENERIC if args.generic else 0)
+            decoders[(name, prec)] = (code, pcm, decs[prec])
         for pi, e in enumerate(points):
-            llr, cw, d_o = gen_point(name, args.frames, e, seed=1000 * 2 + 10 * ci + pi)
+            llr, cw, d_o = gen_point(name, args.frames, e, seed=seed_base + 10 * ci + pi)
             F = llr.shape[0]
-            out = (torch.empty((F, dec.W64), dtype=torch.int64, device=dev),
-                   torch.empty(F, dtype=torch.uint8, device=dev),
-                   torch.empty(F, dtype=torch.uint8, device=dev),
-                   torch.empty(max(1, dec.workspace_size(F)), dtype=torch.uint8, device=dev))
-            work.append((name, e, dec, torch.from_numpy(llr).to(dev), torch.from_numpy(d_o).to(dev), cw, out,
-                         llr, d_o))
+            llr_d = torch.from_numpy(llr).to(dev)
+            d_o_d = torch.from_numpy(d_o).to(dev)
+            for prec in precisions:
+                dec = decs[prec]
+                if prec == "fix8":
+                    inp = torch.empty(llr_d.shape, dtype=torch.int8, device=dev)
+                    B.quantize_llr(llr_d, code.N, FIX_SCALE, inp)
+                else:
+                    inp = llr_d
+                out = (torch.empty((F, dec.W64), dtype=torch.int64, device=dev),
+                       torch.empty(F, dtype=torch.uint8, device=dev),
+                       torch.empty(F, dtype=torch.uint8, device=dev),
+                       torch.empty(max(1, dec.workspace_size(F)), dtype=torch.uint8, device=dev))
+                work.append((name, e, dec, inp, d_o_d, cw, out, llr[:64].copy(), d_o[:64].copy(), prec))
+            del llr, llr_d
     torch.cuda.synchronize()
     gen_s = time.time() - t0
     total_frames = sum(w[3].shape[0] for w in work)
 
     def step(events=None):
-        for k, (name, e, dec, llr, d_o, cw, out, _, _) in enumerate(work):
+        for k, (name, e, dec, llr, d_o, cw, out, _, _, _) in enumerate(work):
             if events is not None:
                 events[k][0].record(stream)
             dec.decode_into(llr, d_o, out[0], out[1], out[2], workspace=out[3], stream=stream)
@@ -126,21 +154,26 @@ def main():
     # per-point error rates and iteration totals (from the last step's outputs)
     per_point = []
     ops_total = 0.0
-    for k, (name, e, dec, llr, d_o, cw, out, _, _) in enumerate(work):
-        code, pcm, _ = decoders[name]
+    time_by_prec = {}
+    frames_by_prec = {}
+    for k, (name, e, dec, llr, d_o, cw, out, _, _, prec) in enumerate(work):
+        code, pcm, _ = decoders[(name, prec)]
         words = B.unpack_bits(out[0].cpu().numpy().view(np.uint64), code.N)
         iters = out[1].cpu().numpy().astype(np.int64)
         conv = out[2].cpu().numpy().astype(bool)
         err = (words != cw).any(1)
-        per_point.append({"code": name, "ebn0": e, "fer": float(err.mean()),
+        time_by_prec[prec] = time_by_prec.get(prec, 0.0) + launch_ms[:, k].sum() / 1e3 / args.steps
+        frames_by_prec[prec] = frames_by_prec.get(prec, 0) + len(err)
+        per_point.append({"code": name, "precision": prec, "ebn0": e, "fer": float(err.mean()),
                           "ber": float((words != cw).mean()), "avg_iters": float(iters.mean()),
                           "undetected": float((err & conv).mean()),
                           "launch_ms": float(np.median(launch_ms[:, k]))})
         ops_total += iters.sum() * alg_ops_per_iteration(code.N, code.K, pcm.M, pcm.E, 9)
+    
     kernel_s = launch_ms.sum() / 1e3 / args.steps
     achieved = ops_total / kernel_s
     frames_per_s = total_frames * args.steps / elapsed
-    info_bits = sum(w[3].shape[0] * decoders[w[0]][0].K for w in work)
+    info_bits = sum(w[3].shape[0] * decoders[(w[0], w[9])][0].K for w in work)
     res = {
         "metric": "decoded frames/s & info Gbit/s at matched FER vs oracle; p50/p99 latency",
         "value": frames_per_s,
@@ -154,11 +187,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "configs[1]: BCH(63,45) H_o 33x63 and BCH(63,36) H_o 122x63, enhanced NMS "
-                               "9 branches, restart mode, alpha 0.75, max 8 iterations, FP32, %d frames per "
-                               "point, Eb/N0 %s dB" % (args.frames, args.ebn0),
+        "config": {"workload": "%s, %d frames per point, Eb/N0 %s dB" % (wdesc, args.frames, args.ebn0),
                    "frames_per_step": total_frames,
-                   "specialised_kernel": {n: bool(decoders[n][2].specialized) for n in decoders}},
+                   "specialised_kernel": {"%s/%s" % n: bool(decoders[n][2].specialized) for n in decoders}},
+        "frames_per_s_by_precision": {p: frames_by_prec[p] / time_by_prec[p] for p in time_by_prec},
         "info_gbit_s": info_bits * args.steps / elapsed / 1e9,
         "latency_ms": {"per_launch_p50": float(np.percentile(launch_ms, 50)),
                        "per_launch_p99": float(np.percentile(launch_ms, 99)),
@@ -168,8 +200,13 @@ def main():
         "points": per_point,
         "input_generation_s": gen_s,
     }
+    if len(precisions) > 1:
+        fer = {(p["code"], p["ebn0"], p["precision"]): p["fer"] for p in per_point}
+        res["fix8_fer_loss"] = [{"code": c, "ebn0": e, "fer_fp32": fer[(c, e, "fp32")], "fer_fix8": fer[(c, e, "fix8")]}
+                                for (c, e, p) in fer if p == "fp32"]
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(work, decoders, args.cpu_seconds, frames_per_s)
+        res["cpu_baseline"] = cpu_baseline([w for w in work if w[9] == "fp32"], decoders, args.cpu_seconds,
+                                           frames_per_s)
     print(json.dumps(res))
 
 
@@ -181,11 +218,11 @@ def cpu_baseline(work, decoders, budget_s, gpu_fps):
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     per = 64
     sample = []
-    for (name, e, dec, llr, d_o, cw, out, llr_h, d_o_h) in work:
+    for (name, e, dec, llr, d_o, cw, out, llr_h, d_o_h, prec) in work:
         sample.append((name, llr_h[:per], d_o_h[:per], out))
     mats = {}
-    for name in decoders:
-        code, pcm, _ = decoders[name]
+    for (name, prec) in decoders:
+        code, pcm, _ = decoders[(name, prec)]
         m, p, t = synth.CODES[name]
         oc = oracle.Code(m, p, t)
         mats[name] = (pcm.dense(), oc.Hstd)

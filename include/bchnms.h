@@ -164,6 +164,30 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
                          uint8_t *flags, void *y_trace, void *workspace,
                          size_t ws_bytes, hipStream_t stream);
 
+/* Tuning of a specialised decoder (autotuner hook): frames per range handed
+ * to a persistent wave (0: 256) and waves per CU of the persistent grid (0:
+ * the kernel's default).  Changes bch_decode_workspace_size.  No effect on
+ * the generic kernel.  Not thread-safe against a concurrent decode. */
+int bch_decoder_set_tuning(bch_decoder dec, int range_frames, int waves_per_cu);
+
+/* ------------------------------------------------------------------------
+ * Mixed-code batch: the frames of up to BCH_MAX_MIX codes interleaved in one
+ * array; frame f is decoded by decs[code_idx[f]] (frames with code_idx >=
+ * n_codes are left untouched).  Every decoder needs a specialised kernel and
+ * all share the precision.  llr: device [F][ld] with ld >= every N; bits:
+ * device [F][bits_ld] uint64, bits_ld >= every ceil(N/64); iters, flags: as
+ * bch_nms_decode_batch.  One prepass and one persistent kernel per code are
+ * enqueued on stream (no host synchronisation, no memset: the call can be
+ * captured in a HIP graph and replayed).  Per-frame results do not depend on
+ * the mix: each frame decodes exactly as alone.
+ */
+#define BCH_MAX_MIX 8
+size_t bch_mixed_workspace_size(const bch_decoder *decs, int n_codes, int64_t F);
+int bch_mixed_decode_batch(const bch_decoder *decs, int n_codes, const uint8_t *code_idx, const void *llr,
+                           int64_t ld, int64_t F, const uint8_t *d_o, uint64_t *bits, int64_t bits_ld,
+                           uint8_t *iters, uint8_t *flags, void *workspace, size_t ws_bytes,
+                           hipStream_t stream);
+
 /* Syndrome test of eq. 5 with the code's standard PCM: ok[f] = 1 iff
  * H c_f^T = 0.  bits: device [F][ceil(N/64)] uint64; ok: device [F] uint8. */
 int bch_syndrome_check(bch_code code, const uint64_t *bits, int64_t F, uint8_t *ok,

@@ -27,8 +27,10 @@ SYMBOLS = [
     "bch_build_pcm", "bch_pcm_from_dense", "bch_pcm_info", "bch_pcm_export", "bch_pcm_destroy",
     "bch_make_automorphisms", "bch_decoder_create", "bch_decoder_is_specialized",
     "bch_decoder_destroy", "bch_decode_workspace_size", "bch_nms_decode_batch",
-    "bch_syndrome_check", "bch_quantize_llr", "bch_osd_decode",
+    "bch_syndrome_check", "bch_quantize_llr", "bch_osd_decode", "bch_decoder_set_tuning",
+    "bch_mixed_workspace_size", "bch_mixed_decode_batch",
 ]
+MAX_MIX = 8
 
 
 class BchError(RuntimeError):
@@ -81,6 +83,10 @@ def lib():
     L.bch_syndrome_check.argtypes = [P, P, i64, P, P]
     L.bch_quantize_llr.argtypes = [P, i64, i64, i32, ctypes.c_float, P, i64, P]
     L.bch_osd_decode.argtypes = [P, P, i64, i64, i32, P, P, i32]
+    L.bch_decoder_set_tuning.argtypes = [P, i32, i32]
+    L.bch_mixed_workspace_size.argtypes = [P, i32, i64]
+    L.bch_mixed_workspace_size.restype = ctypes.c_size_t
+    L.bch_mixed_decode_batch.argtypes = [P, i32, P, P, i64, i64, P, P, i64, P, P, P, ctypes.c_size_t, P]
     _lib = L
     return L
 
@@ -193,6 +199,11 @@ class Decoder:
     def specialized(self) -> bool:
         return bool(lib().bch_decoder_is_specialized(self.h))
 
+    def set_tuning(self, range_frames: int = 0, waves_per_cu: int = 0):
+        """Frames per persistent-wave range and waves per CU (0: defaults)."""
+        _check(lib().bch_decoder_set_tuning(self.h, range_frames, waves_per_cu), "bch_decoder_set_tuning")
+        self.tuning = (range_frames, waves_per_cu)
+
     def workspace_size(self, F: int) -> int:
         return int(lib().bch_decode_workspace_size(self.h, F))
 
@@ -229,6 +240,40 @@ class Decoder:
         if getattr(self, "h", None) and _lib is not None:
             _lib.bch_decoder_destroy(self.h)
             self.h = None
+
+
+class MixedDecoder:
+    """Frames of several codes interleaved in one batch (one prepass and one
+    persistent kernel per code, all enqueued on one stream)."""
+
+    def __init__(self, decoders):
+        if not 1 <= len(decoders) <= MAX_MIX:
+            raise BchError("a mix takes 1..%d decoders" % MAX_MIX)
+        self.decoders = list(decoders)
+        self._arr = (ctypes.c_void_p * len(decoders))(*[d.h.value for d in decoders])
+        self.ld = 128 if max(d.N for d in decoders) > 64 else 64
+        self.W64 = max(d.W64 for d in decoders)
+
+    def workspace_size(self, F: int) -> int:
+        return int(lib().bch_mixed_workspace_size(self._arr, len(self.decoders), F))
+
+    def decode_into(self, code_idx, llr, d_o, bits, iters, flags, workspace, stream=None):
+        F, ld = llr.shape
+        ws_bytes = workspace.numel() * workspace.element_size()
+        _check(lib().bch_mixed_decode_batch(self._arr, len(self.decoders), _dptr(code_idx), _dptr(llr), ld, F,
+                                            _dptr(d_o), _dptr(bits), bits.shape[1], _dptr(iters), _dptr(flags),
+                                            _dptr(workspace), ws_bytes, _stream(stream)), "bch_mixed_decode_batch")
+
+    def decode(self, code_idx, llr, d_o, stream=None):
+        import torch
+        F = llr.shape[0]
+        dev = llr.device
+        bits = torch.zeros((F, self.W64), dtype=torch.int64, device=dev)
+        iters = torch.zeros(F, dtype=torch.uint8, device=dev)
+        flags = torch.zeros(F, dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(1, self.workspace_size(F)), dtype=torch.uint8, device=dev)
+        self.decode_into(code_idx, llr, d_o, bits, iters, flags, ws, stream)
+        return bits, iters, flags
 
 
 def syndrome_check(code: Code, bits, ok, stream=None):

@@ -28,6 +28,7 @@ struct bch_decoder_s {
     int msyn = 0;
     int n_cu = 0;
     int range_frames = 256;
+    int waves = 0;  // waves per CU of the persistent grid (0: the kernel's default)
     const bch::SpecKernel *spec = nullptr;
 };
 
@@ -87,6 +88,55 @@ static int code_hsyn(bch_code_s *code, uint64_t **out)
     c.d_hsyn_dev = dev;
     *out = d;
     return BCH_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int waves_of(const bch_decoder_s *d)
+{
+    return d->waves > 0 ? d->waves : d->spec->waves_per_cu;
+}
+
+// device workspace of one specialised decode of up to F frames
+static size_t spec_ws_bytes(const bch_decoder_s *d, int64_t F)
+{
+    size_t n = align256(bucket_ws_bytes(F, shift_period(d->N), d->range_frames));
+    if (d->spec->y_global)
+        n += align256((size_t)d->n_cu * waves_of(d) * d->N * 64 * sizeof(float));
+    return n;
+}
+
+// prepass + persistent kernel of one decoder; code_idx / code select the
+// frames of a mixed batch (code_idx may be null: every frame)
+static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int64_t F, const uint8_t *d_o,
+                       const uint8_t *code_idx, int code, uint64_t *bits, int64_t bits_ld, uint8_t *iters,
+                       uint8_t *flags, void *trace, void *workspace, hipStream_t stream)
+{
+    const int dp = shift_period(d->N);
+    char *ws = static_cast<char *>(workspace);
+    BucketWs w = bucket_ws_carve(ws, F, dp, d->range_frames);
+    hipError_t e = launch_bucketing(d_o, code_idx, code, F, dp, d->prm.n_branches > 1, d->range_frames, w, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "bucketing prepass");
+    SpecLaunch s{};
+    s.llr = llr;
+    s.ld = ld;
+    s.order = w.order;
+    s.ranges = w.ranges;
+    s.n_ranges = w.n_ranges;
+    s.range_counter = w.range_counter;
+    s.bits = bits;
+    s.bits_ld = bits_ld;
+    s.iters = iters;
+    s.flags = flags;
+    s.trace = trace;
+    s.yscratch = d->spec->y_global
+                     ? reinterpret_cast<float *>(ws + align256(bucket_ws_bytes(F, dp, d->range_frames)))
+                     : nullptr;
+    s.max_iter = d->prm.max_iter;
+    s.alpha = d->prm.alpha;
+    e = d->spec->launch(s, d->n_cu, waves_of(d), stream);
+    return e == hipSuccess ? BCH_OK : hip_fail(e, "specialised kernel launch");
 }
 
 }  // namespace bch
@@ -352,12 +402,8 @@ size_t bch_decode_workspace_size(bch_decoder dec, int64_t F)
 {
     if (!dec || F < 0)
         return 0;
-    if (dec->spec) {
-        size_t n = bucket_ws_bytes(F, shift_period(dec->N), dec->range_frames);
-        if (dec->spec->y_global)
-            n += (size_t)dec->n_cu * dec->spec->waves_per_cu * dec->N * 64 * sizeof(float) + 256;
-        return n;
-    }
+    if (dec->spec)
+        return spec_ws_bytes(dec, F);
     if (dec->prm.mode == BCH_MODE_RESTART)
         return 0;
     size_t n = (size_t)dec->prm.n_branches * dec->E * F;
@@ -390,33 +436,9 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess || cur != dec->dev)
         return fail(BCH_EINVAL, "decoder belongs to another device");
-    if (dec->spec) {
-        const int dp = shift_period(dec->N);
-        BucketWs w = bucket_ws_carve(workspace, F, dp, dec->range_frames);
-        hipError_t e = launch_bucketing(d_o, F, dp, dec->prm.n_branches > 1, dec->range_frames, w, stream);
-        if (e != hipSuccess)
-            return hip_fail(e, "bucketing prepass");
-        SpecLaunch s{};
-        s.llr = llr;
-        s.ld = ld;
-        s.order = w.order;
-        s.ranges = w.ranges;
-        s.n_ranges = w.n_ranges;
-        s.range_counter = w.range_counter;
-        s.bits = bits;
-        s.iters = iters;
-        s.flags = flags;
-        s.trace = y_trace;
-        s.yscratch = nullptr;
-        if (dec->spec->y_global) {
-            uintptr_t p = reinterpret_cast<uintptr_t>(workspace) + bucket_ws_bytes(F, dp, dec->range_frames);
-            s.yscratch = reinterpret_cast<float *>((p + 255) & ~(uintptr_t)255);
-        }
-        s.max_iter = dec->prm.max_iter;
-        s.alpha = dec->prm.alpha;
-        e = dec->spec->launch(s, dec->n_cu, stream);
-        return e == hipSuccess ? BCH_OK : hip_fail(e, "specialised kernel launch");
-    }
+    if (dec->spec)
+        return spec_decode(dec, llr, ld, F, d_o, nullptr, 0, bits, dec->W64, iters, flags, y_trace, workspace,
+                           stream);
     GenericArgs a{};
     a.llr = llr;
     a.ld = ld;
@@ -445,6 +467,72 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
     a.ws_s = ws ? ws + (size_t)a.B * a.E * F : nullptr;
     hipError_t e = launch_generic_fp32(a, stream);
     return e == hipSuccess ? BCH_OK : hip_fail(e, "generic kernel launch");
+}
+
+int bch_decoder_set_tuning(bch_decoder dec, int range_frames, int waves_per_cu)
+{
+    if (!dec)
+        return fail(BCH_EINVAL, "decoder is NULL");
+    if (range_frames != 0 && (range_frames < 64 || range_frames > (1 << 20)))
+        return fail(BCH_EINVAL, "range_frames must be 0 or in [64, 2^20]");
+    if (waves_per_cu < 0 || waves_per_cu > 16)
+        return fail(BCH_EINVAL, "waves_per_cu must be in [0, 16]");
+    dec->range_frames = range_frames ? range_frames : 256;
+    dec->waves = waves_per_cu;
+    return BCH_OK;
+}
+
+size_t bch_mixed_workspace_size(const bch_decoder *decs, int n_codes, int64_t F)
+{
+    if (!decs || n_codes < 1 || n_codes > BCH_MAX_MIX || F < 0)
+        return 0;
+    size_t n = 0;
+    for (int c = 0; c < n_codes; c++) {
+        if (!decs[c] || !decs[c]->spec)
+            return 0;
+        n += spec_ws_bytes(decs[c], F);
+    }
+    return n;
+}
+
+int bch_mixed_decode_batch(const bch_decoder *decs, int n_codes, const uint8_t *code_idx, const void *llr,
+                           int64_t ld, int64_t F, const uint8_t *d_o, uint64_t *bits, int64_t bits_ld,
+                           uint8_t *iters, uint8_t *flags, void *workspace, size_t ws_bytes, hipStream_t stream)
+{
+    if (!decs || n_codes < 1 || n_codes > BCH_MAX_MIX)
+        return fail(BCH_EINVAL, "n_codes must be in [1, BCH_MAX_MIX]");
+    if (F < 0 || F > (int64_t)1 << 31)
+        return fail(BCH_EINVAL, "F out of range");
+    if (F == 0)
+        return BCH_OK;
+    if (!code_idx || !llr || !d_o || !bits || !iters || !flags)
+        return fail(BCH_EINVAL, "NULL buffer");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess)
+        return fail(BCH_EDEVICE, "hipGetDevice failed");
+    for (int c = 0; c < n_codes; c++) {
+        const bch_decoder_s *d = decs[c];
+        if (!d || !d->spec)
+            return fail(BCH_EUNSUPPORTED, "every decoder of a mixed batch needs a specialised kernel");
+        if (d->dev != cur)
+            return fail(BCH_EINVAL, "decoder belongs to another device");
+        if (d->prm.precision != decs[0]->prm.precision)
+            return fail(BCH_EINVAL, "decoders of a mixed batch must share the precision");
+        if (ld < d->N || bits_ld < d->W64)
+            return fail(BCH_EINVAL, "ld or bits_ld too small for a code of the mix");
+    }
+    const size_t need = bch_mixed_workspace_size(decs, n_codes, F);
+    if (!workspace || ws_bytes < need)
+        return fail(BCH_ENOMEM, "workspace too small");
+    char *ws = static_cast<char *>(workspace);
+    for (int c = 0; c < n_codes; c++) {
+        int rc = spec_decode(decs[c], llr, ld, F, d_o, code_idx, c, bits, bits_ld, iters, flags, nullptr, ws,
+                             stream);
+        if (rc)
+            return rc;
+        ws += spec_ws_bytes(decs[c], F);
+    }
+    return BCH_OK;
 }
 
 int bch_syndrome_check(bch_code code, const uint64_t *bits, int64_t F, uint8_t *ok,

@@ -9,6 +9,7 @@
 //      block (LDS counters).
 // Frames keep their input order inside a (block, bucket) up to the LDS-atomic
 // ranks; no result depends on that order (every frame is decoded on its own).
+// With a code index, only the frames of one code of a mixed batch are taken.
 #include <hip/hip_runtime.h>
 
 #include "spec_launch.h"
@@ -27,8 +28,9 @@ __device__ __forceinline__ int bucket_of(const uint8_t *d_o, int64_t f, int dp, 
     return use ? (int)d_o[f] % dp : 0;
 }
 
-__global__ void __launch_bounds__(TPB) bucket_count(const uint8_t *__restrict__ d_o, int64_t F, int dp,
-                                                    int use, int *__restrict__ blk_hist)
+__global__ void __launch_bounds__(TPB) bucket_count(const uint8_t *__restrict__ d_o,
+                                                    const uint8_t *__restrict__ code_idx, int code, int64_t F,
+                                                    int dp, int use, int *__restrict__ blk_hist)
 {
     __shared__ int h[MAXB];
     if (threadIdx.x < MAXB)
@@ -37,7 +39,7 @@ __global__ void __launch_bounds__(TPB) bucket_count(const uint8_t *__restrict__ 
     const int64_t base = (int64_t)blockIdx.x * BLK;
     for (int k = threadIdx.x; k < BLK; k += TPB) {
         const int64_t f = base + k;
-        if (f < F)
+        if (f < F && (!code_idx || code_idx[f] == code))
             atomicAdd(&h[bucket_of(d_o, f, dp, use)], 1);
     }
     __syncthreads();
@@ -106,8 +108,9 @@ __global__ void __launch_bounds__(SCAN) bucket_scan(int *__restrict__ blk_hist, 
     }
 }
 
-__global__ void __launch_bounds__(TPB) bucket_place(const uint8_t *__restrict__ d_o, int64_t F, int dp,
-                                                    int use, const int *__restrict__ blk_off, BucketWs w)
+__global__ void __launch_bounds__(TPB) bucket_place(const uint8_t *__restrict__ d_o,
+                                                    const uint8_t *__restrict__ code_idx, int code, int64_t F,
+                                                    int dp, int use, const int *__restrict__ blk_off, BucketWs w)
 {
     __shared__ int h[MAXB];
     if (threadIdx.x < MAXB)
@@ -116,7 +119,7 @@ __global__ void __launch_bounds__(TPB) bucket_place(const uint8_t *__restrict__ 
     const int64_t base = (int64_t)blockIdx.x * BLK;
     for (int k = threadIdx.x; k < BLK; k += TPB) {
         const int64_t f = base + k;
-        if (f < F) {
+        if (f < F && (!code_idx || code_idx[f] == code)) {
             const int pos = atomicAdd(&h[bucket_of(d_o, f, dp, use)], 1);
             w.order[pos] = (int)f;
         }
@@ -155,15 +158,17 @@ BucketWs bucket_ws_carve(void *ws, int64_t F, int dp, int range_frames)
     return w;
 }
 
-hipError_t launch_bucketing(const uint8_t *d_o, int64_t F, int dp, int use_offsets, int range_frames,
-                            const BucketWs &w, hipStream_t stream)
+hipError_t launch_bucketing(const uint8_t *d_o, const uint8_t *code_idx, int code, int64_t F, int dp,
+                            int use_offsets, int range_frames, const BucketWs &w, hipStream_t stream)
 {
     if (dp > MAXB || F <= 0)
         return hipErrorInvalidValue;
     const int nblk = (int)n_blocks(F);
-    hipLaunchKernelGGL(bucket_count, dim3(nblk), dim3(TPB), 0, stream, d_o, F, dp, use_offsets, w.blk_hist);
+    hipLaunchKernelGGL(bucket_count, dim3(nblk), dim3(TPB), 0, stream, d_o, code_idx, code, F, dp, use_offsets,
+                       w.blk_hist);
     hipLaunchKernelGGL(bucket_scan, dim3(1), dim3(SCAN), 0, stream, w.blk_hist, nblk, dp, range_frames, w);
-    hipLaunchKernelGGL(bucket_place, dim3(nblk), dim3(TPB), 0, stream, d_o, F, dp, use_offsets, w.blk_hist, w);
+    hipLaunchKernelGGL(bucket_place, dim3(nblk), dim3(TPB), 0, stream, d_o, code_idx, code, F, dp, use_offsets,
+                       w.blk_hist, w);
     return hipGetLastError();
 }
 

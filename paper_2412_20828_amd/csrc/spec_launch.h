@@ -14,7 +14,8 @@ struct SpecLaunch {
     const int4 *ranges;    // {start, end, d_o, 0} slices of order
     const int *n_ranges;
     int *range_counter;    // next range to hand out (zeroed by the prepass)
-    uint64_t *bits;        // [F][W64]
+    uint64_t *bits;        // [F][bits_ld] (bits_ld >= W64)
+    int64_t bits_ld;
     uint8_t *iters;        // [F]
     uint8_t *flags;        // [F]
     void *trace;           // [F][max_iter][ld] float32 / int32, or null
@@ -38,7 +39,8 @@ struct BucketWs {
 
 size_t bucket_ws_bytes(int64_t F, int dp, int range_frames);
 BucketWs bucket_ws_carve(void *ws, int64_t F, int dp, int range_frames);
-hipError_t launch_bucketing(const uint8_t *d_o, int64_t F, int dp, int use_offsets, int range_frames,
-                            const BucketWs &w, hipStream_t stream);
+// code_idx (may be null): only frames with code_idx[f] == code are taken.
+hipError_t launch_bucketing(const uint8_t *d_o, const uint8_t *code_idx, int code, int64_t F, int dp,
+                            int use_offsets, int range_frames, const BucketWs &w, hipStream_t stream);
 
 }  // namespace bch

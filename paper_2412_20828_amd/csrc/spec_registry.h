@@ -19,7 +19,7 @@ struct SpecKernel {
     int waves_per_cu;  // persistent grid = CUs x waves_per_cu wavefronts
     int y_global;      // 1: y lives in device scratch [grid][N][64] floats
     const char *name;
-    hipError_t (*launch)(const SpecLaunch &, int n_cu, hipStream_t);
+    hipError_t (*launch)(const SpecLaunch &, int n_cu, int waves_per_cu, hipStream_t);
 };
 
 uint64_t pcm_fingerprint(const Pcm &p);

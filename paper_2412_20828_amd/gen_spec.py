@@ -215,7 +215,7 @@ def generate(stage1_lib: str, out_dir: str):
             fh.write('#define SPEC_BODY "%s"\n' % os.path.basename(body_path))
             fh.write('#include "nms_spec_fp32.inc"\n')
         srcs.append(src_path)
-        decls.append("namespace %s { hipError_t launch(const SpecLaunch &, int, hipStream_t); }" % ns)
+        decls.append("namespace %s { hipError_t launch(const SpecLaunch &, int, int, hipStream_t); }" % ns)
         entries.append("    {0x%016xull, %d, %d, %d, %d, %d, %d, %d, \"%s\", &%s::launch}," %
                        (fingerprint(H), N, M, B, mode, prec, waves, 1 if N > 64 else 0, ns, ns))
     table = "\n".join(decls) + "\nstatic const SpecKernel kSpecKernels[] = {\n" + "\n".join(entries) + \

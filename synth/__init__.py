@@ -146,3 +146,34 @@ def mixed_draws(F: int, seed: int, probs, ebn0_lo: float, ebn0_hi: float, block:
     idx = r.choice(len(probs), size=F, p=np.asarray(probs, dtype=np.float64))
     e = r.uniform(ebn0_lo, ebn0_hi, size=F)
     return idx.astype(np.int32), e
+
+
+@dataclass
+class MixedFrames:
+    llr: np.ndarray        # [F][ld] float32, ld = the widest code's row stride
+    code_idx: np.ndarray   # [F] uint8 index into names
+    codewords: np.ndarray  # [F][N_max] uint8 (zero beyond the frame's N)
+    d_o: np.ndarray        # [F] uint8
+    ebn0: np.ndarray       # [F] float64
+
+
+def mixed_frames(names, F: int, seed: int, probs, ebn0_lo: float, ebn0_hi: float, block: int = 0) -> MixedFrames:
+    """F frames of several codes interleaved: code and Eb/N0 drawn per frame
+    (mixed_draws), then each code's frames generated by frames() at those
+    Eb/N0 values and placed at their positions."""
+    idx, e = mixed_draws(F, seed, probs, ebn0_lo, ebn0_hi, block)
+    specs = [code(n) for n in names]
+    ld = max(s.ld for s in specs)
+    nmax = max(s.N for s in specs)
+    llr = np.zeros((F, ld), dtype=np.float32)
+    cw = np.zeros((F, nmax), dtype=np.uint8)
+    d_o = np.zeros(F, dtype=np.uint8)
+    for k, n in enumerate(names):
+        sel = np.nonzero(idx == k)[0]
+        if sel.size == 0:
+            continue
+        fr = frames(n, sel.size, e[sel], seed, block)
+        llr[sel, :fr.llr.shape[1]] = fr.llr
+        cw[sel, :specs[k].N] = fr.codewords
+        d_o[sel] = fr.d_o
+    return MixedFrames(llr, idx.astype(np.uint8), cw, d_o, e)

@@ -268,3 +268,132 @@ def test_fixed_point_without_kernel_is_rejected(B):
     q = torch.zeros((64, 64), dtype=torch.int8, device="cuda")
     with pytest.raises(B.BchError):
         dec.decode(q)
+
+
+# ------------------------------------------------------------ mixed-code batches
+MIX = [("bch127_64", 72), ("bch127_99", 33), ("bch63_36", 122)]
+MIX_P = [0.5, 0.25, 0.25]
+
+
+def mixed_setup(B, precision, F, seed, lo=1.5, hi=5.0):
+    objs = [lib_objects(B, n, r) for n, r in MIX]
+    decs = [B.Decoder(c, p, n_branches=9, max_iter=8, precision=precision) for c, p in objs]
+    assert all(d.specialized for d in decs)
+    mf = synth.mixed_frames([n for n, _ in MIX], F, seed, MIX_P, lo, hi)
+    llr = torch.from_numpy(mf.llr).cuda()
+    if precision == B.FIX8:
+        q = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
+        for k, (c, _) in enumerate(objs):
+            qk = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
+            B.quantize_llr(llr, c.N, 4.0, qk)
+            sel = torch.from_numpy(mf.code_idx == k).cuda()
+            q[sel] = qk[sel]
+        llr = q
+    return objs, decs, mf, llr
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mixed_batch_equals_each_code_alone(B, precision):
+    """Interleaved frames of three codes in one call give, frame by frame,
+    exactly the words, iteration counts and flags of each code's own call."""
+    F = 3000
+    objs, decs, mf, llr = mixed_setup(B, precision, F, seed=17)
+    mix = B.MixedDecoder(decs)
+    ci = torch.from_numpy(mf.code_idx).cuda()
+    d_o = torch.from_numpy(mf.d_o).cuda()
+    bits, iters, flg = mix.decode(ci, llr, d_o)
+    torch.cuda.synchronize()
+    for k, dec in enumerate(decs):
+        sel = torch.from_numpy(np.nonzero(mf.code_idx == k)[0]).cuda()
+        ab, ai, af, _ = dec.decode(llr[sel].contiguous(), d_o[sel].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(bits[sel][:, :dec.W64], ab)
+        assert torch.equal(iters[sel], ai) and torch.equal(flg[sel], af)
+        assert int(ai.min()) >= 1
+
+
+def test_mixed_batch_against_oracle(B):
+    """Mixed FP32 batch against the FP64 oracle of every code (parity bar of
+    the single-code tests), and the fixed-point mix bit-exact against the
+    integer oracle."""
+    F = 1200
+    for precision in (0, 1):
+        objs, decs, mf, llr = mixed_setup(B, precision, F, seed=23)
+        mix = B.MixedDecoder(decs)
+        bits, iters, flg = mix.decode(torch.from_numpy(mf.code_idx).cuda(), llr, torch.from_numpy(mf.d_o).cuda())
+        torch.cuda.synchronize()
+        bh, ih, fh = bits.cpu().numpy().view(np.uint64), iters.cpu().numpy(), flg.cpu().numpy()
+        lh = llr.cpu().numpy()
+        for k, (name, rows) in enumerate(MIX):
+            sel = np.nonzero(mf.code_idx == k)[0]
+            oc = oracle_code(name)
+            H = oracle_hopt(name, rows)
+            N = oc.N
+            w = B.unpack_bits(bh[sel][:, :(N + 63) // 64], N)
+            if precision == 0:
+                res = oracle.decode_batch(H, oc.Hstd, lh[sel], mf.d_o[sel], 9, 0.75, 8, oracle.R1,
+                                          threads=8, trace=True)
+                compare_with_oracle(w, ih[sel], fh[sel], None, *res)
+            else:
+                ow, oit, ocv = oracle.decode_batch(H, oc.Hstd, lh[sel], mf.d_o[sel], 9, 0.75, 8, oracle.R1,
+                                                   kind=oracle.KIND_FIXED, threads=8)
+                assert np.array_equal(w, ow) and np.array_equal(ih[sel], oit)
+                assert np.array_equal(fh[sel].astype(bool), ocv)
+
+
+def test_mixed_batch_rejections(B):
+    objs, decs, mf, llr = mixed_setup(B, 0, 64, seed=3)
+    c, p = lib_objects(B, "bch63_45", 0)
+    generic = B.Decoder(c, p, n_branches=1, mode=B.MODE_EXTRINSIC, max_iter=4)
+    ci = torch.from_numpy(mf.code_idx).cuda()
+    d_o = torch.from_numpy(mf.d_o).cuda()
+    with pytest.raises(B.BchError):
+        B.MixedDecoder(decs + [generic]).decode(ci, llr, d_o)          # no specialised kernel
+    fix = B.Decoder(*lib_objects(B, "bch63_45", 33), n_branches=9, max_iter=8, precision=B.FIX8)
+    with pytest.raises(B.BchError):
+        B.MixedDecoder(decs + [fix]).decode(ci, llr, d_o)              # precision differs
+    with pytest.raises(B.BchError):
+        B.MixedDecoder(decs).decode(ci, llr[:, :64].contiguous(), d_o)  # ld < 127
+    # frames whose index names no decoder are left untouched
+    ci2 = ci.clone()
+    ci2[::2] = 7
+    bits, iters, flg = B.MixedDecoder(decs).decode(ci2, llr, d_o)
+    torch.cuda.synchronize()
+    assert int(iters[::2].max()) == 0 and int(iters[1::2].min()) >= 1
+
+
+def test_mixed_batch_graph_replay(B):
+    """The mixed call captured in a HIP graph and replayed several times, with
+    new inputs copied in and eager work between replays: every replay equals
+    the eager call on the same inputs."""
+    F = 4096
+    objs, decs, mf, llr = mixed_setup(B, 0, F, seed=31)
+    mix = B.MixedDecoder(decs)
+    ci = torch.from_numpy(mf.code_idx).cuda()
+    d_o = torch.from_numpy(mf.d_o).cuda()
+    bits = torch.zeros((F, 2), dtype=torch.int64, device="cuda")
+    iters = torch.zeros(F, dtype=torch.uint8, device="cuda")
+    flg = torch.zeros(F, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(mix.workspace_size(F), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        mix.decode_into(ci, llr, d_o, bits, iters, flg, ws, stream=s)  # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        mix.decode_into(ci, llr, d_o, bits, iters, flg, ws, stream=torch.cuda.current_stream())
+    for rep in range(4):
+        nf = synth.mixed_frames([n for n, _ in MIX], F, 100 + rep, MIX_P, 1.5, 5.0)
+        llr.copy_(torch.from_numpy(nf.llr))
+        ci.copy_(torch.from_numpy(nf.code_idx))
+        d_o.copy_(torch.from_numpy(nf.d_o))
+        bits.zero_()
+        iters.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        eb, ei, ef = mix.decode(ci, llr, d_o)
+        torch.cuda.synchronize()
+        assert torch.equal(bits, eb) and torch.equal(iters, ei) and torch.equal(flg, ef), rep

@@ -45,3 +45,18 @@ def test_per_frame_snr():
     e = np.linspace(1.5, 5.0, 64)
     fr = synth.frames("bch63_36", 64, e, seed=2)
     assert np.allclose(fr.ebn0, e)
+
+
+def test_mixed_frames_place_each_code_at_its_positions():
+    names = ["bch127_64", "bch127_99", "bch63_36"]
+    mf = synth.mixed_frames(names, 500, 5, [0.5, 0.25, 0.25], 1.5, 5.0)
+    assert mf.llr.shape == (500, 128) and mf.code_idx.shape == (500,)
+    assert set(np.unique(mf.code_idx)) == {0, 1, 2}
+    for k, n in enumerate(names):
+        sel = np.nonzero(mf.code_idx == k)[0]
+        fr = synth.frames(n, sel.size, mf.ebn0[sel], 5)
+        assert np.array_equal(mf.llr[sel, :fr.llr.shape[1]], fr.llr)
+        assert (mf.d_o[sel] < synth.code(n).d_p).all()
+        N = synth.code(n).N
+        assert not mf.llr[sel, N:].any() and not mf.codewords[sel, N:].any()
+    assert (mf.ebn0 >= 1.5).all() and (mf.ebn0 <= 5.0).all()
