@@ -1,0 +1,122 @@
+"""Autotuner of the specialised decoders' launch shape.
+
+Knobs: frames per range handed to a persistent wave (the unit of work a wave
+takes from the range counter) and waves per CU of the persistent grid.  The
+tuner times every candidate on a synthetic batch of the decoder's own code at
+a given Eb/N0 and keeps the fastest; results are cached in tuning.json beside
+this file, keyed by (code, rows of H_o, precision, branches, GPU name), and
+applied by apply_cached().
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(_HERE, "tuning.json")
+RANGE_FRAMES = [128, 256, 512, 1024, 2048]
+WAVES = [0, 2, 3, 4, 5, 6, 8]
+
+
+def key(code_name: str, rows: int, precision: int, n_branches: int, gpu: str) -> str:
+    return "%s/m%d/%s/b%d/%s" % (code_name, rows, "fix8" if precision else "fp32", n_branches, gpu)
+
+
+def _gpu_name():
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def load():
+    if os.path.exists(CACHE):
+        with open(CACHE) as fh:
+            return json.load(fh)
+    return {}
+
+
+def apply_cached(decoder, code_name: str, rows: int) -> bool:
+    entry = load().get(key(code_name, rows, decoder.precision, decoder.n_branches, _gpu_name()))
+    if not entry or not decoder.specialized:
+        return False
+    decoder.set_tuning(entry["range_frames"], entry["waves_per_cu"])
+    return True
+
+
+def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 400_000, reps: int = 3,
+         seed: int = 99, write: bool = True):
+    """Time every candidate and return the best (also cached when write)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from . import binding as B
+    fr = synth.frames(code_name, frames, ebn0, seed=seed)
+    llr = torch.from_numpy(fr.llr).cuda()
+    if decoder.precision == B.FIX8:
+        q = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
+        B.quantize_llr(llr, decoder.N, 4.0, q)
+        llr = q
+    d_o = torch.from_numpy(fr.d_o).cuda()
+    F = frames
+    bits = torch.empty((F, decoder.W64), dtype=torch.int64, device="cuda")
+    it = torch.empty(F, dtype=torch.uint8, device="cuda")
+    fl = torch.empty(F, dtype=torch.uint8, device="cuda")
+    results = []
+    for rf in RANGE_FRAMES:
+        for wv in WAVES:
+            decoder.set_tuning(rf, wv)
+            ws = torch.empty(max(1, decoder.workspace_size(F)), dtype=torch.uint8, device="cuda")
+            decoder.decode_into(llr, d_o, bits, it, fl, workspace=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                decoder.decode_into(llr, d_o, bits, it, fl, workspace=ws)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            results.append((dt, rf, wv))
+    results.sort()
+    dt, rf, wv = results[0]
+    decoder.set_tuning(rf, wv)
+    best = {"range_frames": rf, "waves_per_cu": wv, "frames_per_s": F / dt, "ebn0": ebn0,
+            "default_frames_per_s": F / next(d for d, r, w in results if r == 256 and w == 0)}
+    if write:
+        cache = load()
+        cache[key(code_name, rows, decoder.precision, decoder.n_branches, _gpu_name())] = best
+        with open(CACHE, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+    return best, results
+
+
+def main():
+    global CACHE
+    import argparse
+    ap = argparse.ArgumentParser(description="tune the specialised decoders' launch shape")
+    ap.add_argument("--codes", default="bch127_64:72,bch127_99:33,bch63_36:122,bch63_45:33")
+    ap.add_argument("--precisions", default="fp32,fix8")
+    ap.add_argument("--ebn0", type=float, default=3.0)
+    ap.add_argument("--frames", type=int, default=400_000)
+    ap.add_argument("--out", default=CACHE, help="JSON cache to update")
+    args = ap.parse_args()
+    CACHE = args.out
+    from . import binding as B
+    for spec in args.codes.split(","):
+        name, rows = spec.split(":")
+        rows = int(rows)
+        d = B.CODE_DEFS[name]
+        code = B.Code(d.m, d.prim, d.t)
+        pcm = B.Pcm.build(code, target_rows=rows, seed=1)
+        for prec in args.precisions.split(","):
+            dec = B.Decoder(code, pcm, n_branches=9, max_iter=8, precision=B.FIX8 if prec == "fix8" else B.FP32)
+            if not dec.specialized:
+                print("%s/%d/%s: no specialised kernel, skipped" % (name, rows, prec), flush=True)
+                continue
+            best, res = tune(dec, name, rows, ebn0=args.ebn0, frames=args.frames)
+            print("%s/%d/%s: best range %d waves %d: %.1fM frames/s (default %.1fM)" % (
+                name, rows, prec, best["range_frames"], best["waves_per_cu"], best["frames_per_s"] / 1e6,
+                best["default_frames_per_s"] / 1e6), flush=True)
+
+
+if __name__ == "__main__":
+    main()

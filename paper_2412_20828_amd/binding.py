@@ -58,6 +58,10 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise BchError("libbchnms.so is not built: run python -m paper_2412_20828_amd.build")
+    # torch ships its own libamdhip64.so.7 (same soname as the system one): load
+    # it first so that the library binds to torch's HIP runtime; otherwise the
+    # process ends up with the system runtime and torch's HSA and sees no GPU
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
     L.bch_last_error.restype = ctypes.c_char_p
