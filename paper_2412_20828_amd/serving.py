@@ -1,0 +1,332 @@
+"""Continuous-batching decode service with the hybrid NMS + OSD back end.
+
+Requests (frames of one code, channel LLRs on the host, one cyclic offset per
+frame) arrive at any time.  The engine keeps every code's decoder (matrix
+and branch tables) resident on the device and owns a fixed set of slots,
+each a preallocated batch of pinned host staging, device buffers and a HIP
+stream.  Whenever a slot is free, the pending requests are packed into it in
+arrival order up to the slot's frame capacity (admission by memory: a slot
+never holds more than it was sized for) and the whole batch is decoded in one
+mixed-code call; slots run on their own streams, so the batch of a newly
+admitted request overlaps on the device with the batches already in flight.
+When a slot's results are back, frames whose syndrome is still nonzero are
+handed to a pool of host threads running order-p OSD on the channel LLRs (the
+hybrid of Section II-B and the complexity account C_t = C_1 + F_1 C_2 of
+Section IV); a request completes when all of its frames have a decision.
+
+Every frame decodes exactly as it would alone: the kernel's arithmetic for a
+frame depends only on that frame's LLRs and offset, and OSD is deterministic.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import binding as B
+
+FLAG_CONVERGED = 1
+FLAG_OSD = 2
+
+
+@dataclass
+class Request:
+    code: int                  # index into the engine's code list
+    llr: np.ndarray            # [F][ld] float32 channel LLRs (host)
+    d_o: np.ndarray            # [F] uint8 cyclic offsets
+    rid: int = 0
+    arrival: float = 0.0       # time.perf_counter() at submission (set by submit when 0)
+    bits: np.ndarray = None    # [F][2] uint64 decisions (bit i of word i // 64)
+    iters: np.ndarray = None   # [F] NMS iterations
+    flags: np.ndarray = None   # [F] FLAG_CONVERGED | FLAG_OSD
+    t_admit: float = 0.0
+    t_gpu: float = 0.0
+    t_done: float = 0.0
+    n_osd: int = 0
+    _osd_left: int = 0
+
+    @property
+    def frames(self) -> int:
+        return self.llr.shape[0]
+
+
+@dataclass
+class _Slot:
+    stream: object
+    event: object
+    h_llr: object
+    h_ci: object
+    h_do: object
+    d_llr: object
+    d_ci: object
+    d_do: object
+    d_bits: object
+    d_iters: object
+    d_flags: object
+    h_bits: object
+    h_iters: object
+    h_flags: object
+    ws: object
+    members: list = field(default_factory=list)   # (request, offset)
+    busy: bool = False
+
+
+class Engine:
+    """codes: [(name, rows of H_o)].  slot_frames: capacity of one slot (at
+    least the largest request).  osd_order: order of the host OSD stage (None
+    disables the hybrid); a request's failed frames are split into chunks of
+    osd_chunk frames spread over osd_workers host threads.  tuned: apply the
+    autotuner's cached launch shapes."""
+
+    def __init__(self, codes, slot_frames=1 << 16, n_slots=3, osd_order=2, osd_workers=8,
+                 precision=B.FP32, max_iter=8, tuned=True, device="cuda", osd_chunk=16):
+        import torch
+        self.torch = torch
+        self.dev = torch.device(device)
+        self.names = [n for n, _ in codes]
+        self.codes, self.decs = [], []
+        for name, rows in codes:
+            d = B.CODE_DEFS[name]
+            code = B.Code(d.m, d.prim, d.t)
+            pcm = B.Pcm.build(code, target_rows=rows, seed=1)
+            dec = B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=max_iter,
+                            precision=precision)
+            if not dec.specialized:
+                raise B.BchError("%s with %d rows has no specialised kernel" % (name, rows))
+            if tuned:
+                from . import autotune
+                autotune.apply_cached(dec, name, rows)
+            self.codes.append((code, pcm))
+            self.decs.append(dec)
+        if precision != B.FP32:
+            raise B.BchError("the service takes FP32 LLRs (quantise per code for int8 decoders)")
+        self.mix = B.MixedDecoder(self.decs)
+        self._mixes = {}
+        self.cap = slot_frames
+        self.ld = self.mix.ld
+        self.osd_order = osd_order
+        self.osd_chunk = osd_chunk
+        self.pending = collections.deque()
+        self.osd_pool = ThreadPoolExecutor(osd_workers) if osd_order is not None else None
+        self.osd_jobs = []
+        ws_bytes = max(1, self.mix.workspace_size(slot_frames))
+        self.slots = []
+        for _ in range(n_slots):
+            pin = dict(pin_memory=True)
+            cap, ld = slot_frames, self.ld
+            self.slots.append(_Slot(
+                stream=torch.cuda.Stream(device=self.dev), event=torch.cuda.Event(),
+                h_llr=torch.empty((cap, ld), dtype=torch.float32, **pin),
+                h_ci=torch.empty(cap, dtype=torch.uint8, **pin), h_do=torch.empty(cap, dtype=torch.uint8, **pin),
+                d_llr=torch.empty((cap, ld), dtype=torch.float32, device=self.dev),
+                d_ci=torch.empty(cap, dtype=torch.uint8, device=self.dev),
+                d_do=torch.empty(cap, dtype=torch.uint8, device=self.dev),
+                d_bits=torch.zeros((cap, 2), dtype=torch.int64, device=self.dev),
+                d_iters=torch.empty(cap, dtype=torch.uint8, device=self.dev),
+                d_flags=torch.empty(cap, dtype=torch.uint8, device=self.dev),
+                h_bits=torch.empty((cap, 2), dtype=torch.int64, **pin),
+                h_iters=torch.empty(cap, dtype=torch.uint8, **pin), h_flags=torch.empty(cap, dtype=torch.uint8, **pin),
+                ws=torch.empty(ws_bytes, dtype=torch.uint8, device=self.dev)))
+        self.launches = 0
+        self.frames_launched = 0
+
+    # ------------------------------------------------------------ client side
+    def submit(self, req: Request):
+        if not 0 <= req.code < len(self.decs):
+            raise B.BchError("unknown code index %d" % req.code)
+        if req.frames > self.cap:
+            raise B.BchError("request of %d frames exceeds the slot capacity %d" % (req.frames, self.cap))
+        if req.llr.shape[1] < self.codes[req.code][0].N:
+            raise B.BchError("LLR rows shorter than the code length")
+        if not req.arrival:
+            req.arrival = time.perf_counter()
+        self.pending.append(req)
+
+    def busy(self) -> bool:
+        return bool(self.pending or self.osd_jobs or any(s.busy for s in self.slots))
+
+    # ------------------------------------------------------------ scheduler
+    def poll(self):
+        """One scheduler pass: collect finished slots (hand failures to OSD),
+        collect finished OSD jobs, then admit pending requests into free slots.
+        Returns the requests completed in this pass."""
+        done = []
+        for s in self.slots:
+            if s.busy and s.event.query():
+                done += self._finish_slot(s)
+        if self.osd_jobs:
+            still = []
+            for fut, req in self.osd_jobs:
+                if fut.done():
+                    req.t_done = max(req.t_done, fut.result())
+                    req._osd_left -= 1
+                    if req._osd_left == 0:
+                        done.append(req)
+                else:
+                    still.append((fut, req))
+            self.osd_jobs = still
+        for s in self.slots:
+            if not self.pending:
+                break
+            if not s.busy:
+                self._launch(s)
+        return done
+
+    def drain(self, sleep=0.0):
+        out = []
+        while self.busy():
+            out += self.poll()
+            if sleep:
+                time.sleep(sleep)
+        return out
+
+    def _launch(self, s: _Slot):
+        torch = self.torch
+        n = 0
+        s.members = []
+        hl, hc, hd = s.h_llr.numpy(), s.h_ci.numpy(), s.h_do.numpy()
+        now = time.perf_counter()
+        present = sorted({r.code for r in self._admissible()})
+        local = {c: k for k, c in enumerate(present)}
+        while self.pending and n + self.pending[0].frames <= self.cap:
+            r = self.pending.popleft()
+            F, w = r.frames, min(r.llr.shape[1], self.ld)
+            hl[n:n + F, :w] = r.llr[:, :w]
+            hc[n:n + F] = local[r.code]
+            hd[n:n + F] = r.d_o
+            r.t_admit = now
+            s.members.append((r, n))
+            n += F
+        if n == 0:
+            return
+        with torch.cuda.stream(s.stream):
+            s.d_llr[:n].copy_(s.h_llr[:n], non_blocking=True)
+            s.d_ci[:n].copy_(s.h_ci[:n], non_blocking=True)
+            s.d_do[:n].copy_(s.h_do[:n], non_blocking=True)
+            self._mix(present).decode_into(s.d_ci[:n], s.d_llr[:n], s.d_do[:n], s.d_bits[:n], s.d_iters[:n],
+                                           s.d_flags[:n], s.ws, stream=s.stream)
+            s.h_bits[:n].copy_(s.d_bits[:n], non_blocking=True)
+            s.h_iters[:n].copy_(s.d_iters[:n], non_blocking=True)
+            s.h_flags[:n].copy_(s.d_flags[:n], non_blocking=True)
+            s.event.record(s.stream)
+        s.busy = True
+        self.launches += 1
+        self.frames_launched += n
+
+    def _admissible(self):
+        """The pending requests the next launch takes (arrival order, up to
+        the slot capacity)."""
+        n = 0
+        for r in self.pending:
+            if n + r.frames > self.cap:
+                break
+            n += r.frames
+            yield r
+
+    def _mix(self, present):
+        """Mixed decoder over the codes present in a batch (kernels are
+        enqueued only for those codes)."""
+        key = tuple(present)
+        m = self._mixes.get(key)
+        if m is None:
+            m = self._mixes[key] = B.MixedDecoder([self.decs[c] for c in present])
+        return m
+
+    def _finish_slot(self, s: _Slot):
+        done = []
+        now = time.perf_counter()
+        hb = s.h_bits.numpy().view(np.uint64)
+        hi, hf = s.h_iters.numpy(), s.h_flags.numpy()
+        for r, off in s.members:
+            F = r.frames
+            W = self.decs[r.code].W64
+            r.bits = np.zeros((F, 2), np.uint64)
+            r.bits[:, :W] = hb[off:off + F, :W]
+            r.iters = hi[off:off + F].copy()
+            r.flags = hf[off:off + F].copy() & FLAG_CONVERGED
+            r.t_gpu = now
+            failed = np.nonzero(r.flags == 0)[0]
+            r.n_osd = int(failed.size)
+            if r.n_osd and self.osd_pool is not None:
+                chunks = [failed[k:k + self.osd_chunk] for k in range(0, failed.size, self.osd_chunk)]
+                r._osd_left = len(chunks)
+                for ch in chunks:
+                    self.osd_jobs.append((self.osd_pool.submit(self._osd, r, ch), r))
+            else:
+                r.t_done = now
+                done.append(r)
+        s.members = []
+        s.busy = False
+        return done
+
+    def _osd(self, r: Request, idx: np.ndarray) -> float:
+        """OSD of some of a request's failed frames (one host thread);
+        returns the completion time."""
+        code = self.codes[r.code][0]
+        out = B.osd_decode(code, r.llr[idx], self.osd_order, n_threads=1)
+        r.bits[idx, :out.shape[1]] = out
+        r.flags[idx] |= FLAG_OSD
+        return time.perf_counter()
+
+    def close(self):
+        if self.osd_pool is not None:
+            self.osd_pool.shutdown(wait=True)
+
+
+def decode_alone(engine: Engine, req: Request):
+    """Reference path for one request: its code's decoder on its frames alone,
+    then host OSD on the failed frames (same back end as the service)."""
+    torch = engine.torch
+    dec = engine.decs[req.code]
+    code = engine.codes[req.code][0]
+    llr = torch.from_numpy(np.ascontiguousarray(req.llr)).to(engine.dev)
+    d_o = torch.from_numpy(np.ascontiguousarray(req.d_o)).to(engine.dev)
+    bits, iters, flags, _ = dec.decode(llr, d_o)
+    torch.cuda.synchronize()
+    F = req.frames
+    out = np.zeros((F, 2), np.uint64)
+    out[:, :dec.W64] = bits.cpu().numpy().view(np.uint64)
+    fl = flags.cpu().numpy() & FLAG_CONVERGED
+    failed = np.nonzero(fl == 0)[0]
+    if failed.size and engine.osd_order is not None:
+        out[failed, :dec.W64] = B.osd_decode(code, req.llr[failed], engine.osd_order, n_threads=1)
+        fl[failed] |= FLAG_OSD
+    return out, iters.cpu().numpy(), fl
+
+
+def run_trace(engine: Engine, reqs, offsets):
+    """Replay requests in real time: request k is submitted offsets[k] seconds
+    after the start (all at once when offsets are zero).  Returns the
+    completed requests and the wall time from the first submission to the
+    last completion."""
+    order = np.argsort(np.asarray(offsets), kind="stable")
+    t0 = time.perf_counter()
+    k = 0
+    done = []
+    max_busy = 0
+    while k < len(order) or engine.busy():
+        now = time.perf_counter() - t0
+        while k < len(order) and offsets[order[k]] <= now:
+            r = reqs[order[k]]
+            r.arrival = t0 + offsets[order[k]]
+            engine.submit(r)
+            k += 1
+        done += engine.poll()
+        max_busy = max(max_busy, sum(s.busy for s in engine.slots))
+        time.sleep(0)  # let the OSD threads take the interpreter lock
+    wall = max(r.t_done for r in done) - t0
+    engine.max_busy_slots = max_busy
+    return done, wall
+
+
+def summarize(done, wall):
+    lat = np.array([r.t_done - r.arrival for r in done]) * 1e3
+    frames = sum(r.frames for r in done)
+    osd = sum(r.n_osd for r in done)
+    return {"requests": len(done), "frames": frames, "wall_s": wall, "frames_per_s": frames / wall,
+            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+            "latency_ms_mean": float(lat.mean()), "osd_share": osd / max(1, frames),
+            "gpu_latency_ms_p50": float(np.percentile([(r.t_gpu - r.arrival) * 1e3 for r in done], 50))}

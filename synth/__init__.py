@@ -177,3 +177,28 @@ def mixed_frames(names, F: int, seed: int, probs, ebn0_lo: float, ebn0_hi: float
         cw[sel, :specs[k].N] = fr.codewords
         d_o[sel] = fr.d_o
     return MixedFrames(llr, idx.astype(np.uint8), cw, d_o, e)
+
+
+@dataclass
+class RequestDraw:
+    t: float               # arrival time at unit rate (seconds x requests/s)
+    code: int              # index into names
+    frames: int            # 1..2^max_log2, log-uniform
+    ebn0: float            # dB, one value per request
+
+
+def request_trace(n: int, seed: int, n_codes: int, ebn0_lo: float, ebn0_hi: float, max_log2: int = 12):
+    """n requests of a Poisson stream at unit rate (divide t by the rate in
+    requests/s): exponential gaps, size round(2^(max_log2 U)), code uniform,
+    Eb/N0 uniform per request."""
+    r = _rng(seed, 0, 4, 0)
+    t = np.cumsum(r.exponential(1.0, size=n))
+    size = np.rint(2.0 ** (max_log2 * r.uniform(0.0, 1.0, size=n))).astype(np.int64)
+    code_i = r.integers(0, n_codes, size=n)
+    e = r.uniform(ebn0_lo, ebn0_hi, size=n)
+    return [RequestDraw(float(t[k]), int(code_i[k]), int(size[k]), float(e[k])) for k in range(n)]
+
+
+def request_frames(names, draw: RequestDraw, seed: int, rid: int) -> Frames:
+    """The frames of request rid (its own block of the code's streams)."""
+    return frames(names[draw.code], draw.frames, draw.ebn0, seed, block=1000 + rid)

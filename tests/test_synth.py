@@ -60,3 +60,19 @@ def test_mixed_frames_place_each_code_at_its_positions():
         N = synth.code(n).N
         assert not mf.llr[sel, N:].any() and not mf.codewords[sel, N:].any()
     assert (mf.ebn0 >= 1.5).all() and (mf.ebn0 <= 5.0).all()
+
+
+def test_request_trace_distribution():
+    tr = synth.request_trace(20000, 1, 4, 2.0, 5.0)
+    t = np.array([d.t for d in tr])
+    gaps = np.diff(t)
+    assert abs(gaps.mean() - 1.0) < 0.03 and abs(gaps.std() - 1.0) < 0.05   # exponential, rate 1
+    sz = np.array([d.frames for d in tr])
+    assert sz.min() >= 1 and sz.max() <= 4096
+    lg = np.log2(sz[sz > 8])                                                  # log-uniform body
+    assert abs(np.mean(lg) - (3 + 12) / 2) < 0.15
+    assert set(np.unique([d.code for d in tr])) == {0, 1, 2, 3}
+    e = np.array([d.ebn0 for d in tr])
+    assert e.min() >= 2.0 and e.max() <= 5.0
+    fr = synth.request_frames(["bch63_36", "bch63_45", "bch127_64", "bch127_99"], tr[5], 1, 5)
+    assert fr.llr.shape[0] == tr[5].frames
