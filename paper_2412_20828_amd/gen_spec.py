@@ -17,14 +17,14 @@ import numpy as np
 # (code name, target rows of H_o, n_branches, mode, precision (0 FP32, 1 FIX8),
 #  waves per CU of the persistent grid)
 SPECS = [
-    ("bch63_45", 33, 9, 1, 0, 5),
-    ("bch63_36", 122, 9, 1, 0, 4),
-    ("bch63_36", 32, 9, 1, 0, 5),
+    ("bch63_45", 33, 9, 1, 0, 8),
+    ("bch63_36", 122, 9, 1, 0, 8),
+    ("bch63_36", 32, 9, 1, 0, 8),
     ("bch127_99", 33, 9, 1, 0, 4),
     ("bch127_64", 72, 9, 1, 0, 4),
     ("bch127_78", 57, 9, 1, 0, 4),
-    ("bch63_45", 33, 9, 1, 1, 5),
-    ("bch63_36", 122, 9, 1, 1, 4),
+    ("bch63_45", 33, 9, 1, 1, 8),
+    ("bch63_36", 122, 9, 1, 1, 8),
     ("bch127_99", 33, 9, 1, 1, 4),
     ("bch127_64", 72, 9, 1, 1, 4),
 ]
@@ -87,7 +87,20 @@ def fingerprint(H: np.ndarray) -> int:
     return h
 
 
-def body_source(H: np.ndarray) -> str:
+def _min(a, b):
+    """min(a, b) as med3(a, b, -inf): the same value for non-NaN inputs, and
+    unlike fminf it needs no canonicalised copies of its operands (which
+    would double the live registers of the magnitude array)."""
+    return "__builtin_amdgcn_fmed3f(%s, %s, -__builtin_inff())" % (a, b)
+
+
+def _max(a, b):
+    return "__builtin_amdgcn_fmed3f(%s, %s, __builtin_inff())" % (a, b)
+
+
+def body_source(H: np.ndarray, accumulate: bool = False) -> str:
+    """Row function of the FP32 decoder.  accumulate: add every edge's c2v into
+    T (T holds a running sum over branches) instead of overwriting T."""
     M, N = H.shape
     W32 = (N + 31) // 32
     out = ["__device__ __forceinline__ void body(const float *__restrict__ A, "
@@ -103,26 +116,26 @@ def body_source(H: np.ndarray) -> str:
         out.append("        const uint32_t cnt = %s;" % cnt)
         out.append("        const float sg = __uint_as_float(0x3f800000u | (cnt << 31));")
         c0, c1 = cols[0], cols[1]
-        out.append("        float m1 = fminf(A[%d], A[%d]), m2 = fmaxf(A[%d], A[%d]);" % (c0, c1, c0, c1))
+        out.append("        float m1 = %s, m2 = %s;" % (_min("A[%d]" % c0, "A[%d]" % c1), _max("A[%d]" % c0, "A[%d]" % c1)))
         for c in cols[2:]:
-            out.append("        m2 = __builtin_amdgcn_fmed3f(m1, m2, A[%d]); m1 = fminf(m1, A[%d]);" % (c, c))
+            out.append("        m2 = __builtin_amdgcn_fmed3f(m1, m2, A[%d]); m1 = %s;" % (c, _min("m1", "A[%d]" % c)))
         out.append("        const float P = m1 + m2;")
         for c in cols:
             mag = "__builtin_amdgcn_fmed3f(m1, m2, P - A[%d])" % c
-            if touched[c]:
+            if touched[c] or accumulate:
                 out.append("        T[%d] = __builtin_fmaf(sg, %s, T[%d]);" % (c, mag, c))
             else:
                 out.append("        T[%d] = sg * %s;" % (c, mag))
                 touched[c] = True
         out.append("    }")
     for c in range(N):
-        if not touched[c]:
+        if not touched[c] and not accumulate:
             out.append("    T[%d] = 0.0f;" % c)
     out.append("}")
     return "\n".join(out)
 
 
-def body_source_fix8(H: np.ndarray) -> str:
+def body_source_fix8(H: np.ndarray, accumulate: bool = False) -> str:
     """Row function of the fixed-point decoder.  A holds the int8-saturated
     magnitudes (integers 0..127 held exactly as floats).  The c2v magnitude is
     (3m + 2) >> 2 = floor(0.75 m + 0.5) of the row's other-entry minimum m;
@@ -145,22 +158,22 @@ def body_source_fix8(H: np.ndarray) -> str:
         out.append("        const uint32_t cnt = %s;" % cnt)
         out.append("        const float sg = __uint_as_float(0x3f800000u | (cnt << 31));")
         c0, c1 = cols[0], cols[1]
-        out.append("        float m1 = fminf(A[%d], A[%d]), m2 = fmaxf(A[%d], A[%d]);" % (c0, c1, c0, c1))
+        out.append("        float m1 = %s, m2 = %s;" % (_min("A[%d]" % c0, "A[%d]" % c1), _max("A[%d]" % c0, "A[%d]" % c1)))
         for c in cols[2:]:
-            out.append("        m2 = __builtin_amdgcn_fmed3f(m1, m2, A[%d]); m1 = fminf(m1, A[%d]);" % (c, c))
+            out.append("        m2 = __builtin_amdgcn_fmed3f(m1, m2, A[%d]); m1 = %s;" % (c, _min("m1", "A[%d]" % c)))
         out.append("        const float q1 = floorf(__builtin_fmaf(m1, 0.75f, 0.5f)), "
                    "q2 = floorf(__builtin_fmaf(m2, 0.75f, 0.5f));")
         out.append("        const float K = __builtin_fmaf(m1, 128.0f, q2);")
         for c in cols:
             mag = "__builtin_amdgcn_fmed3f(q1, q2, __builtin_fmaf(A[%d], -128.0f, K))" % c
-            if touched[c]:
+            if touched[c] or accumulate:
                 out.append("        T[%d] = __builtin_fmaf(sg, %s, T[%d]);" % (c, mag, c))
             else:
                 out.append("        T[%d] = sg * %s;" % (c, mag))
                 touched[c] = True
         out.append("    }")
     for c in range(N):
-        if not touched[c]:
+        if not touched[c] and not accumulate:
             out.append("    T[%d] = 0.0f;" % c)
     out.append("}")
     return "\n".join(out)
@@ -203,15 +216,18 @@ def generate(stage1_lib: str, out_dir: str):
         M, N = H.shape
         ns = "spec_%s_m%d_b%d%s" % (name, M, B, "_fix8" if prec else "")
         body_path = os.path.join(out_dir, ns + "_body.inc")
+        regacc = 1 if N <= 64 and B > 1 else 0
         with open(body_path, "w") as fh:
             fh.write("// generated: %s, H_o %d x %d, %d edges\n" % (name, M, N, int(H.sum())))
-            fh.write((body_source_fix8(H) if prec else body_source(H)) + "\n\n" + syndrome_source(Hs) + "\n")
+            fh.write((body_source_fix8(H, regacc) if prec else body_source(H, regacc)) + "\n\n" +
+                     syndrome_source(Hs) + "\n")
         src_path = os.path.join(out_dir, ns + ".hip")
         with open(src_path, "w") as fh:
             fh.write('#include "spec_launch.h"\n')
             yg = 1 if N > 64 else 0
             fh.write("#define SPEC_N %d\n#define SPEC_B %d\n#define SPEC_NS %s\n#define SPEC_WAVES %d\n"
-                     "#define SPEC_Y_GLOBAL %d\n#define SPEC_FIX8 %d\n" % (N, B, ns, waves, yg, prec))
+                     "#define SPEC_Y_GLOBAL %d\n#define SPEC_FIX8 %d\n#define SPEC_REGACC %d\n"
+                     % (N, B, ns, waves, yg, prec, regacc))
             fh.write('#define SPEC_BODY "%s"\n' % os.path.basename(body_path))
             fh.write('#include "nms_spec_fp32.inc"\n')
         srcs.append(src_path)
