@@ -61,10 +61,10 @@ FIX_SCALE = 4.0
 # x 1.0).  It holds only for the kernel sources the counters were taken on
 # (hash of the kernel template, its launch header and the row-function
 # generator); any other build reports traffic null.
-TRAFFIC_SRC_HASH = "614e7e205e4abb73"
+TRAFFIC_SRC_HASH = "c54594ebebd46184"
 TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written) bytes per frame
-    "spec_bch63_36_m122_b9": (267.33, 55.53),
-    "spec_bch63_45_m33_b9": (264.06, 53.94),
+    "spec_bch63_36_m122_b9": (302.09, 182.74),
+    "spec_bch63_45_m33_b9": (263.70, 53.87),
 }
 
 

@@ -165,9 +165,12 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
                          size_t ws_bytes, hipStream_t stream);
 
 /* Tuning of a specialised decoder (autotuner hook): frames per range handed
- * to a persistent wave (0: 256) and waves per CU of the persistent grid (0:
- * the kernel's default).  Changes bch_decode_workspace_size.  No effect on
- * the generic kernel.  Not thread-safe against a concurrent decode. */
+ * to a persistent wave (0: 256; a decode of F frames uses at most
+ * F / (persistent waves), rounded down to a multiple of 64 and at least 64,
+ * so that small batches still reach every wave) and waves per CU of the
+ * persistent grid (0: the kernel's default).  Changes
+ * bch_decode_workspace_size.  No effect on the generic kernel.  Not
+ * thread-safe against a concurrent decode. */
 int bch_decoder_set_tuning(bch_decoder dec, int range_frames, int waves_per_cu);
 
 /* ------------------------------------------------------------------------

@@ -16,7 +16,7 @@ import time
 _HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(_HERE, "tuning.json")
 RANGE_FRAMES = [128, 256, 512, 1024, 2048]
-WAVES = [0, 2, 3, 4, 5, 6, 8]
+WAVES = [0, 2, 3, 4, 5, 6, 8, 10, 12]
 
 
 def key(code_name: str, rows: int, precision: int, n_branches: int, gpu: str) -> str:

@@ -97,10 +97,20 @@ static int waves_of(const bch_decoder_s *d)
     return d->waves > 0 ? d->waves : d->spec->waves_per_cu;
 }
 
+// frames per range of a decode of F frames: the configured size, lowered
+// (not below one wave's 64 frames) so that every persistent wave can get a
+// range when the batch is small
+static int eff_range(const bch_decoder_s *d, int64_t F)
+{
+    const int64_t waves = std::max<int64_t>(1, (int64_t)d->n_cu * waves_of(d));
+    const int64_t r = F / waves / 64 * 64;
+    return (int)std::max<int64_t>(64, std::min<int64_t>(d->range_frames, r));
+}
+
 // device workspace of one specialised decode of up to F frames
 static size_t spec_ws_bytes(const bch_decoder_s *d, int64_t F)
 {
-    size_t n = align256(bucket_ws_bytes(F, shift_period(d->N), d->range_frames));
+    size_t n = align256(bucket_ws_bytes(F, shift_period(d->N), eff_range(d, F)));
     if (d->spec->y_global)
         n += align256((size_t)d->n_cu * waves_of(d) * d->N * 64 * sizeof(float));
     return n;
@@ -114,8 +124,9 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
 {
     const int dp = shift_period(d->N);
     char *ws = static_cast<char *>(workspace);
-    BucketWs w = bucket_ws_carve(ws, F, dp, d->range_frames);
-    hipError_t e = launch_bucketing(d_o, code_idx, code, F, dp, d->prm.n_branches > 1, d->range_frames, w, stream);
+    const int range = eff_range(d, F);
+    BucketWs w = bucket_ws_carve(ws, F, dp, range);
+    hipError_t e = launch_bucketing(d_o, code_idx, code, F, dp, d->prm.n_branches > 1, range, w, stream);
     if (e != hipSuccess)
         return hip_fail(e, "bucketing prepass");
     SpecLaunch s{};
@@ -131,7 +142,7 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
     s.flags = flags;
     s.trace = trace;
     s.yscratch = d->spec->y_global
-                     ? reinterpret_cast<float *>(ws + align256(bucket_ws_bytes(F, dp, d->range_frames)))
+                     ? reinterpret_cast<float *>(ws + align256(bucket_ws_bytes(F, dp, range)))
                      : nullptr;
     s.max_iter = d->prm.max_iter;
     s.alpha = d->prm.alpha;
