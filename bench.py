@@ -36,8 +36,10 @@ sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
 
-# peak of 32-bit vector ALU lane-operations per second: 256 CUs x 64 lanes x 2.4 GHz
-VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# peak of 32-bit vector ALU lane-operations per second: 256 CUs x 128 FP32
+# lanes x 2.4 GHz, the published FP32 vector rate of 157.3 TFLOP/s with an FMA
+# counted as one lane-operation (two FLOPs)
+VALU_PEAK_OPS = 256 * 128 * 2.4e9
 WORKLOADS = {
     # name: (codes with H_o rows, Eb/N0 grid, frames per point, precisions, description)
     "sweep63": ([("bch63_45", 33), ("bch63_36", 122)], "1.0:6.0:0.5", 1_000_000, ["fp32"],
@@ -48,6 +50,8 @@ WORKLOADS = {
                "mode, max 8 iterations, FP32 (alpha 0.75) vs int8 messages (alpha 3/4 shift-add, LLR x 4 "
                "quantised)"),
     "serve": (None, "2.0:5.0", 0, ["fp32"], "serving"),
+    "alpha": (None, "", 0, ["fp32"], "alpha sweep"),
+    "ablation": (None, "", 0, ["fp32"], "branch-count ablation"),
     "mixed": ([("bch127_64", 72), ("bch127_99", 33), ("bch63_36", 122)], "1.5:5.0", 16_000_000, ["fp32", "fix8"],
               "mixed-code batch, per frame 50% BCH(127,64) H_o 72x127, 25% BCH(127,99) H_o 33x127, "
               "25% BCH(63,36) H_o 122x63 in one call, enhanced NMS 9 branches, restart mode, max 8 iterations, "
@@ -161,7 +165,9 @@ def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_ba
         mats[name] = pcm
         decs = {prec: B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8,
                                 precision=B.FIX8 if prec == "fix8" else B.FP32,
-                                flags=B.FORCE_GENERIC if args.generic else 0) for prec in precisions}
+                                flags=(B.FORCE_GENERIC if args.generic else 0) |
+                                (B.PACKED16 if args.packed16 and prec == "fix8" and code.N <= 64 else 0))
+                for prec in precisions}
         for pi, e in enumerate(points):
             llr, cw, d_o = gen_point(name, args.frames, e, seed=seed_base + 10 * ci + pi)
             F = llr.shape[0]
@@ -288,8 +294,8 @@ def run_serve(args):
     from paper_2412_20828_amd import serving
     names = [n for n, _ in SERVE_CODES]
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    eng = serving.Engine(SERVE_CODES, slot_frames=1 << 16, n_slots=3, osd_order=2,
-                         osd_workers=max(1, min(16, threads) - 2), tuned=not args.generic)
+    eng = serving.Engine(SERVE_CODES, slot_frames=1 << 16, n_slots=3, osd_order=2, osd_on=args.osd,
+                         osd_threads=max(1, min(16, threads) - 2), tuned=not args.generic)
     t0 = time.time()
     tr = synth.request_trace(args.requests, 5000, len(names), 2.0, 5.0)
     with ThreadPoolExecutor(min(16, os.cpu_count() or 4)) as ex:
@@ -330,8 +336,9 @@ def run_serve(args):
         "config": {"workload": "serving: %d requests, Poisson arrivals, round(2^(12U)) frames each, code uniform "
                                "over BCH(63,36) H_o 122x63, (63,45) 33x63, (127,64) 72x127, (127,99) 33x127, "
                                "Eb/N0 U[2, 5] dB per request; enhanced NMS 9 branches, max 8 iterations on the "
-                               "GPU (3 slots of 65536 frames), OSD-2 on %d host threads for NMS failures"
-                               % (len(tr), max(1, min(16, threads) - 2)),
+                               "GPU (3 slots of 65536 frames), OSD-2 for NMS failures %s"
+                               % (len(tr), "on the GPU" if args.osd == "device" else
+                                  "on %d host threads" % max(1, min(16, threads) - 2)),
                    "mean_request_frames": mean_frames},
         "saturation": sat,
         "info_gbit_s": None,
@@ -348,6 +355,97 @@ def run_serve(args):
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_hybrid_baseline(eng, tr, frs, names, args.cpu_seconds, sat["frames_per_s"])
     print(json.dumps(res))
+
+
+def timed_decode(dec, llr, d_o, torch, reps=2):
+    """Event-timed decode of one batch (after one warm-up); returns (words,
+    iterations, flags, seconds per decode)."""
+    F = llr.shape[0]
+    bits = torch.empty((F, dec.W64), dtype=torch.int64, device=llr.device)
+    it = torch.empty(F, dtype=torch.uint8, device=llr.device)
+    fl = torch.empty(F, dtype=torch.uint8, device=llr.device)
+    ws = torch.empty(max(1, dec.workspace_size(F)), dtype=torch.uint8, device=llr.device)
+    stream = torch.cuda.current_stream()
+    dec.decode_into(llr, d_o, bits, it, fl, workspace=ws, stream=stream)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        dec.decode_into(llr, d_o, bits, it, fl, workspace=ws, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return bits.cpu().numpy().view(np.uint64), it.cpu().numpy(), fl.cpu().numpy(), a.elapsed_time(b) / 1e3 / reps
+
+
+def run_experiment(args):
+    """Experiments of the method on the GPU kernels.
+
+    alpha: frame error rate against the normalisation factor alpha (eq. 3) at
+    the Eb/N0 where the paper fixes it (2.6 dB for N = 63, 3.0 dB for N = 127),
+    9 branches, restart mode, I_m = 8, 10^6 frames per point; the argmin
+    stands in for the paper's trained, unprinted values.
+
+    ablation: what the automorphism merge buys: plain flooding NMS on the
+    standard H (one branch, extrinsic messages), NMS on H_o (one branch,
+    restart mode), and the 3- and 9-branch enhanced decoders, at 2, 3 and
+    4 dB, 10^6 frames per point: FER, mean iterations and frames/s."""
+    import torch
+
+    from paper_2412_20828_amd import binding as B
+    dev = torch.device("cuda:0")
+    F = args.frames or 1_000_000
+    out = {"metric": "decoded frames/s & info Gbit/s at matched FER vs oracle; p50/p99 latency", "n_gpus": 1,
+           "data": "synthetic", "higher_is_better": True, "vs_baseline": None, "steps": 1, "warmup": 1}
+    rows = []
+    if args.workload == "alpha":
+        alphas = [round(0.5 + 0.05 * k, 2) for k in range(11)]
+        for ci, (name, rows_h, ebn0) in enumerate([("bch63_45", 33, 2.6), ("bch63_36", 122, 2.6),
+                                                   ("bch127_64", 72, 3.0), ("bch127_99", 33, 3.0)]):
+            d = B.CODE_DEFS[name]
+            code = B.Code(d.m, d.prim, d.t)
+            pcm = B.Pcm.build(code, target_rows=rows_h, seed=1)
+            llr_h, cw, d_o_h = gen_point(name, F, ebn0, seed=6000 + ci)
+            truth = pack(cw)
+            llr, d_o = torch.from_numpy(llr_h).to(dev), torch.from_numpy(d_o_h).to(dev)
+            fers = []
+            for a in alphas:
+                dec = B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=a, max_iter=8)
+                w, it, fl, sec = timed_decode(dec, llr, d_o, torch, reps=1)
+                fer = float((w != truth[:, :w.shape[1]]).any(1).mean())
+                fers.append(fer)
+                rows.append({"code": name, "rows": rows_h, "ebn0": ebn0, "alpha": a, "fer": fer,
+                             "avg_iters": float(it.mean()), "frames_per_s": F / sec})
+            best = alphas[int(np.argmin(fers))]
+            rows.append({"code": name, "best_alpha": best, "fer_at_best": min(fers),
+                         "fer_at_0.75": fers[alphas.index(0.75)]})
+        out.update({"workload": "alpha", "config": {"workload": "alpha sweep 0.50:0.05:1.00, 9 branches, restart "
+                                                               "mode, I_m 8, %d frames per point" % F}})
+    else:
+        points = [2.0, 3.0, 4.0]
+        for ci, (name, rows_h) in enumerate([("bch63_45", 33), ("bch63_36", 122)]):
+            d = B.CODE_DEFS[name]
+            code = B.Code(d.m, d.prim, d.t)
+            ho = B.Pcm.build(code, target_rows=rows_h, seed=1)
+            hs = B.Pcm.standard(code)
+            cfgs = [("plain NMS, H_std (%dx63), 1 branch, extrinsic" % hs.M, hs, 1, B.MODE_EXTRINSIC),
+                    ("NMS on H_o, 1 branch, restart", ho, 1, B.MODE_RESTART),
+                    ("enhanced NMS, 3 branches", ho, 3, B.MODE_RESTART),
+                    ("enhanced NMS, 9 branches", ho, 9, B.MODE_RESTART)]
+            for pi, e in enumerate(points):
+                llr_h, cw, d_o_h = gen_point(name, F, e, seed=7000 + 10 * ci + pi)
+                truth = pack(cw)
+                llr, d_o = torch.from_numpy(llr_h).to(dev), torch.from_numpy(d_o_h).to(dev)
+                for label, pcm, nb, mode in cfgs:
+                    dec = B.Decoder(code, pcm, n_branches=nb, mode=mode, alpha=0.75, max_iter=8)
+                    w, it, fl, sec = timed_decode(dec, llr, d_o, torch, reps=1)
+                    rows.append({"code": name, "ebn0": e, "config": label, "specialised_kernel": dec.specialized,
+                                 "fer": float((w != truth[:, :w.shape[1]]).any(1).mean()),
+                                 "avg_iters": float(it.mean()), "frames_per_s": F / sec})
+        out.update({"workload": "ablation", "config": {"workload": "branch-count ablation, alpha 0.75, I_m 8, "
+                                                                  "%d frames per point" % F}})
+    out["rows"] = rows
+    out["value"] = None
+    out["unit"] = "frames/s"
+    print(json.dumps(out))
 
 
 def cpu_hybrid_baseline(eng, tr, frs, names, budget_s, gpu_fps):
@@ -403,7 +501,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--generic", action="store_true", help="force the generic (unspecialised) kernel")
     ap.add_argument("--tuned", action="store_true", help="apply the autotuner's cached launch shapes")
+    ap.add_argument("--precision", default="", choices=["", "fp32", "fix8", "both"],
+                    help="override the workload's precisions")
+    ap.add_argument("--packed16", action="store_true", help="fixed point: the packed 16-bit kernels (N = 63)")
     ap.add_argument("--requests", type=int, default=3000, help="requests of the serving workload")
+    ap.add_argument("--osd", default="device", choices=["device", "host"], help="serving: where OSD-2 runs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -422,6 +524,8 @@ def main():
         sys.exit(2)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload in ("alpha", "ablation"):
+        return run_experiment(args)
 
     import torch
 
@@ -429,6 +533,9 @@ def main():
 
     wl = WORKLOADS[args.workload]
     codes, grid, frames, precisions, wdesc = wl[:5]
+    if args.precision:
+        precisions = ["fp32", "fix8"] if args.precision == "both" else [args.precision]
+        wdesc = wdesc.split(", FP32")[0] + ", precision " + "+".join(precisions)
     args.frames = args.frames or frames
     args.ebn0 = args.ebn0 or grid
     dev = torch.device("cuda:0")

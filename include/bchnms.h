@@ -127,7 +127,10 @@ int bch_make_automorphisms(int N, int n_branches, int d_o, int16_t *maps);
 enum { BCH_MODE_RESTART = 1, BCH_MODE_MEMORY = 2, BCH_MODE_EXTRINSIC = 3 };
 enum { BCH_FP32 = 0, BCH_FIX8 = 1 };
 enum {
-    BCH_DEC_FORCE_GENERIC = 1 /* do not use a PCM-specialised kernel */
+    BCH_DEC_FORCE_GENERIC = 1, /* do not use a PCM-specialised kernel */
+    BCH_DEC_PACKED16 = 2       /* BCH_FIX8 with N = 63: the packed 16-bit kernel (two frames
+                                  per lane, same results); without it the fixed-point kernel
+                                  holds its integers in 32-bit registers */
 };
 typedef struct {
     int n_branches; /* 1, 3 or 9 */
@@ -208,6 +211,27 @@ int bch_quantize_llr(const float *llr, int64_t ld, int64_t F, int N, float scale
  * every decoded frame.  Runs on n_threads host threads (<= 0: all cores). */
 int bch_osd_decode(bch_code code, const float *llr, int64_t ld, int64_t F, int order,
                    const uint8_t *skip, uint64_t *bits, int n_threads);
+
+/* Order-p OSD (Section II-B) on the device: the second stage of the hybrid
+ * decoder of Section IV without leaving the GPU.  Same decisions as
+ * bch_osd_decode (reliabilities |L| in FP64, positions ordered by decreasing
+ * reliability with ties by index, candidates in the order weight 0, 1, 2
+ * with the first of least cost kept).  Uses dec's code (its N, K and
+ * generator); order 0..2.  llr: device [F][ld] float32 channel LLRs (ld >= N);
+ * skip: device [F] uint8 or NULL, frames with skip[f] != 0 are left alone
+ * (pass the decoder's flags to run OSD exactly on the frames whose syndrome
+ * stayed nonzero); bits: device [F][bits_ld] uint64, written for every other
+ * frame.  Enqueued on stream; allocates nothing. */
+int bch_osd_decode_device(bch_decoder dec, const float *llr, int64_t ld, int64_t F, int order,
+                          const uint8_t *skip, uint64_t *bits, int64_t bits_ld, hipStream_t stream);
+
+/* The same over a mixed-code batch (as bch_mixed_decode_batch): frame f is
+ * decoded with decs[code_idx[f]]'s code unless skip[f] != 0 (skip may be
+ * NULL); frames with code_idx >= n_codes are left alone.  One launch per code
+ * on stream; allocates nothing. */
+int bch_mixed_osd_decode(const bch_decoder *decs, int n_codes, const uint8_t *code_idx, const float *llr,
+                         int64_t ld, int64_t F, int order, const uint8_t *skip, uint64_t *bits, int64_t bits_ld,
+                         hipStream_t stream);
 
 #ifdef __cplusplus
 }

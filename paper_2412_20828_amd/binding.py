@@ -21,6 +21,7 @@ BCH_PCM_STD, BCH_PCM_OPT = 0, 1
 MODE_RESTART, MODE_MEMORY, MODE_EXTRINSIC = 1, 2, 3
 FP32, FIX8 = 0, 1
 FORCE_GENERIC = 1
+PACKED16 = 2
 
 SYMBOLS = [
     "bch_last_error", "bch_load_code", "bch_code_info", "bch_code_export", "bch_code_destroy",
@@ -28,7 +29,7 @@ SYMBOLS = [
     "bch_make_automorphisms", "bch_decoder_create", "bch_decoder_is_specialized",
     "bch_decoder_destroy", "bch_decode_workspace_size", "bch_nms_decode_batch",
     "bch_syndrome_check", "bch_quantize_llr", "bch_osd_decode", "bch_decoder_set_tuning",
-    "bch_mixed_workspace_size", "bch_mixed_decode_batch",
+    "bch_mixed_workspace_size", "bch_mixed_decode_batch", "bch_osd_decode_device", "bch_mixed_osd_decode",
 ]
 MAX_MIX = 8
 
@@ -91,6 +92,8 @@ def lib():
     L.bch_mixed_workspace_size.argtypes = [P, i32, i64]
     L.bch_mixed_workspace_size.restype = ctypes.c_size_t
     L.bch_mixed_decode_batch.argtypes = [P, i32, P, P, i64, i64, P, P, i64, P, P, P, ctypes.c_size_t, P]
+    L.bch_osd_decode_device.argtypes = [P, P, i64, i64, i32, P, P, i64, P]
+    L.bch_mixed_osd_decode.argtypes = [P, i32, P, P, i64, i64, i32, P, P, i64, P]
     _lib = L
     return L
 
@@ -240,6 +243,13 @@ class Decoder:
         self.decode_into(llr, d_o, bits, iters, flags, tr, ws, stream)
         return bits, iters, flags, tr
 
+    def osd_into(self, llr, order, bits, skip=None, stream=None):
+        """Device OSD-p of the frames whose skip byte is 0 (all frames when
+        skip is None); bits [F][>= W64] int64 is written for those frames."""
+        F, ld = llr.shape
+        _check(lib().bch_osd_decode_device(self.h, _dptr(llr), ld, F, order, _dptr(skip), _dptr(bits),
+                                           bits.shape[1], _stream(stream)), "bch_osd_decode_device")
+
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.bch_decoder_destroy(self.h)
@@ -267,6 +277,13 @@ class MixedDecoder:
         _check(lib().bch_mixed_decode_batch(self._arr, len(self.decoders), _dptr(code_idx), _dptr(llr), ld, F,
                                             _dptr(d_o), _dptr(bits), bits.shape[1], _dptr(iters), _dptr(flags),
                                             _dptr(workspace), ws_bytes, _stream(stream)), "bch_mixed_decode_batch")
+
+    def osd_into(self, code_idx, llr, order, bits, skip=None, stream=None):
+        """Device OSD-p of every frame whose skip byte is 0, with its own code."""
+        F, ld = llr.shape
+        _check(lib().bch_mixed_osd_decode(self._arr, len(self.decoders), _dptr(code_idx), _dptr(llr), ld, F, order,
+                                          _dptr(skip), _dptr(bits), bits.shape[1], _stream(stream)),
+               "bch_mixed_osd_decode")
 
     def decode(self, code_idx, llr, d_o, stream=None):
         import torch

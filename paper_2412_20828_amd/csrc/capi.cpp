@@ -25,6 +25,7 @@ struct bch_decoder_s {
     uint16_t *d_rowptr = nullptr;
     uint8_t *d_colp = nullptr;
     uint64_t *d_hsyn = nullptr;
+    uint32_t *d_gen = nullptr;  // [K][4] generator rows (device OSD)
     int msyn = 0;
     int n_cu = 0;
     int range_frames = 256;
@@ -98,13 +99,14 @@ static int waves_of(const bch_decoder_s *d)
 }
 
 // frames per range of a decode of F frames: the configured size, lowered
-// (not below one wave's 64 frames) so that every persistent wave can get a
-// range when the batch is small
+// (not below one wave's frames: 64, or 128 for the packed 16-bit kernels) so
+// that every persistent wave can get a range when the batch is small
 static int eff_range(const bch_decoder_s *d, int64_t F)
 {
+    const int64_t fw = d->spec->frames_per_wave;
     const int64_t waves = std::max<int64_t>(1, (int64_t)d->n_cu * waves_of(d));
-    const int64_t r = F / waves / 64 * 64;
-    return (int)std::max<int64_t>(64, std::min<int64_t>(d->range_frames, r));
+    const int64_t r = F / waves / fw * fw;
+    return (int)std::max<int64_t>(fw, std::min<int64_t>(std::max<int64_t>(d->range_frames, fw), r));
 }
 
 // device workspace of one specialised decode of up to F frames
@@ -383,6 +385,16 @@ int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params,
                        hipMemcpyHostToDevice);
     if (he == hipSuccess)
         he = hipMemcpy(d->d_colp, colp.data(), colp.size(), hipMemcpyHostToDevice);
+    std::vector<uint32_t> gen((size_t)c.K * 4, 0u);
+    for (int k = 0; k < c.K; k++)
+        for (int w = 0; w < 2; w++) {
+            gen[(size_t)k * 4 + 2 * w] = (uint32_t)c.G[k].w[w];
+            gen[(size_t)k * 4 + 2 * w + 1] = (uint32_t)(c.G[k].w[w] >> 32);
+        }
+    if (he == hipSuccess)
+        he = hipMalloc(&d->d_gen, gen.size() * sizeof(uint32_t));
+    if (he == hipSuccess)
+        he = hipMemcpy(d->d_gen, gen.data(), gen.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (he != hipSuccess) {
         bch_decoder_destroy(d);
         return hip_fail(he, "decoder tables");
@@ -406,6 +418,8 @@ void bch_decoder_destroy(bch_decoder dec)
         (void)hipFree(dec->d_rowptr);
     if (dec->d_colp)
         (void)hipFree(dec->d_colp);
+    if (dec->d_gen)
+        (void)hipFree(dec->d_gen);
     delete dec;
 }
 
@@ -542,6 +556,86 @@ int bch_mixed_decode_batch(const bch_decoder *decs, int n_codes, const uint8_t *
         if (rc)
             return rc;
         ws += spec_ws_bytes(decs[c], F);
+    }
+    return BCH_OK;
+}
+
+int bch_osd_decode_device(bch_decoder dec, const float *llr, int64_t ld, int64_t F, int order,
+                          const uint8_t *skip, uint64_t *bits, int64_t bits_ld, hipStream_t stream)
+{
+    if (!dec || F < 0 || order < 0 || order > 2)
+        return fail(BCH_EINVAL, "bad argument (order must be 0, 1 or 2)");
+    if (F == 0)
+        return BCH_OK;
+    if (!llr || !bits)
+        return fail(BCH_EINVAL, "NULL buffer");
+    if (ld < dec->N || bits_ld < dec->W64)
+        return fail(BCH_EINVAL, "ld or bits_ld too small");
+    if (dec->N > 128 || dec->K > 128)
+        return fail(BCH_EUNSUPPORTED, "device OSD needs N, K <= 128");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != dec->dev)
+        return fail(BCH_EINVAL, "decoder belongs to another device");
+    OsdArgs a{};
+    a.llr = llr;
+    a.ld = ld;
+    a.F = F;
+    a.skip = skip;
+    a.bits = bits;
+    a.bits_ld = bits_ld;
+    a.G = dec->d_gen;
+    a.N = dec->N;
+    a.K = dec->K;
+    a.order = order;
+    hipError_t e = launch_osd(a, dec->n_cu, stream);
+    return e == hipSuccess ? BCH_OK : hip_fail(e, "device OSD launch");
+}
+
+int bch_mixed_osd_decode(const bch_decoder *decs, int n_codes, const uint8_t *code_idx, const float *llr,
+                         int64_t ld, int64_t F, int order, const uint8_t *skip, uint64_t *bits, int64_t bits_ld,
+                         hipStream_t stream)
+{
+    if (!decs || n_codes < 1 || n_codes > BCH_MAX_MIX)
+        return fail(BCH_EINVAL, "n_codes must be in [1, BCH_MAX_MIX]");
+    if (!code_idx)
+        return fail(BCH_EINVAL, "NULL code_idx");
+    for (int c = 0; c < n_codes; c++) {
+        if (!decs[c])
+            return fail(BCH_EINVAL, "NULL decoder");
+        if (F > 0 && (ld < decs[c]->N || bits_ld < decs[c]->W64))
+            return fail(BCH_EINVAL, "ld or bits_ld too small for a code of the mix");
+    }
+    if (F < 0 || order < 0 || order > 2)
+        return fail(BCH_EINVAL, "bad argument (order must be 0, 1 or 2)");
+    if (F == 0)
+        return BCH_OK;
+    if (!llr || !bits)
+        return fail(BCH_EINVAL, "NULL buffer");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess)
+        return fail(BCH_EDEVICE, "hipGetDevice failed");
+    for (int c = 0; c < n_codes; c++) {
+        const bch_decoder_s *d = decs[c];
+        if (d->dev != cur)
+            return fail(BCH_EINVAL, "decoder belongs to another device");
+        if (d->N > 128 || d->K > 128)
+            return fail(BCH_EUNSUPPORTED, "device OSD needs N, K <= 128");
+        OsdArgs a{};
+        a.llr = llr;
+        a.ld = ld;
+        a.F = F;
+        a.skip = skip;
+        a.code_idx = code_idx;
+        a.code = c;
+        a.bits = bits;
+        a.bits_ld = bits_ld;
+        a.G = d->d_gen;
+        a.N = d->N;
+        a.K = d->K;
+        a.order = order;
+        hipError_t e = launch_osd(a, d->n_cu, stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "device OSD launch");
     }
     return BCH_OK;
 }

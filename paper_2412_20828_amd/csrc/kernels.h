@@ -36,4 +36,19 @@ hipError_t launch_syndrome(const uint64_t *bits, int64_t F, int W64, const uint6
 hipError_t launch_quantize(const float *llr, int64_t ld, int64_t F, int N, float scale,
                            int8_t *q, int64_t ldq, hipStream_t stream);
 
+struct OsdArgs {
+    const float *llr;     // [F][ld] channel LLRs
+    int64_t ld;
+    int64_t F;
+    const uint8_t *skip;  // [F], nonzero: leave the frame alone; or null
+    const uint8_t *code_idx;  // [F] or null: only frames with code_idx[f] == code
+    int code;
+    uint64_t *bits;       // [F][bits_ld]
+    int64_t bits_ld;
+    const uint32_t *G;    // [K][4] generator rows, bit i of row k = word i / 32, bit i % 32
+    int N, K, order;
+};
+
+hipError_t launch_osd(const OsdArgs &a, int n_cu, hipStream_t stream);
+
 }  // namespace bch

@@ -31,8 +31,9 @@ const SpecKernel *find_spec_kernel(const Pcm &p, const bch_dec_params &q)
     for (const SpecKernel &k : kSpecKernels) {
         if (k.launch == nullptr)
             continue;
+        const int variant = (q.flags & BCH_DEC_PACKED16) ? 1 : 0;
         if (k.fingerprint == fp && k.N == p.N && k.M == p.M && k.B == q.n_branches &&
-            k.mode == q.mode && k.precision == q.precision)
+            k.mode == q.mode && k.precision == q.precision && k.variant == variant)
             return &k;
     }
     return nullptr;

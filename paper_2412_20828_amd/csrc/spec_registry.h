@@ -16,8 +16,10 @@ namespace bch {
 struct SpecKernel {
     uint64_t fingerprint;  // of the matrix rows, see pcm_fingerprint()
     int N, M, B, mode, precision;
+    int variant;       // 0, or 1 for the packed 16-bit fixed-point kernel
     int waves_per_cu;  // persistent grid = CUs x waves_per_cu wavefronts
     int y_global;      // 1: y lives in device scratch [grid][N][64] floats
+    int frames_per_wave;  // 64, or 128 for the packed 16-bit kernels
     const char *name;
     hipError_t (*launch)(const SpecLaunch &, int n_cu, int waves_per_cu, hipStream_t);
 };

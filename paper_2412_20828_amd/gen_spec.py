@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 # (code name, target rows of H_o, n_branches, mode, precision (0 FP32, 1 FIX8),
-#  waves per CU of the persistent grid)
+#  waves per CU of the persistent grid[, variant: 1 = packed 16-bit fixed point])
 SPECS = [
     ("bch63_45", 33, 9, 1, 0, 8),
     ("bch63_36", 122, 9, 1, 0, 8),
@@ -27,6 +27,14 @@ SPECS = [
     ("bch63_36", 122, 9, 1, 1, 8),
     ("bch127_99", 33, 9, 1, 1, 4),
     ("bch127_64", 72, 9, 1, 1, 4),
+    # packed 16-bit fixed point, two frames per lane (opt-in variant)
+    ("bch63_45", 33, 9, 1, 1, 8, 1),
+    ("bch63_36", 122, 9, 1, 1, 8, 1),
+    # branch-count ablation (one and three branches, restart mode)
+    ("bch63_45", 33, 3, 1, 0, 8),
+    ("bch63_36", 122, 3, 1, 0, 8),
+    ("bch63_45", 33, 1, 1, 0, 5),
+    ("bch63_36", 122, 1, 1, 0, 4),
 ]
 CODE_DEFS = {
     "bch63_36": (6, 0b1000011, 5),
@@ -179,6 +187,60 @@ def body_source_fix8(H: np.ndarray, accumulate: bool = False) -> str:
     return "\n".join(out)
 
 
+def body_source_pk16(H: np.ndarray, B: int) -> str:
+    """Row function of the packed 16-bit fixed-point decoder: A, T hold two
+    frames per register (v2s), SL / SH their sign bits.  Adds s_j * mag_j(i)
+    into T[i] for every entry; mag = clamp(100 min1 + q2 - 100 A, q1, q2)
+    with q = (3m + 2) >> 2 (any factor above 96 selects q2 exactly at the
+    argmin, and 100 keeps the product a single packed multiply-add)."""
+    M, N = H.shape
+    colw = H.sum(axis=0)
+    if int(colw.max()) * 96 * B > 32767:
+        raise ValueError("16-bit accumulators could overflow: column weight %d, %d branches" % (colw.max(), B))
+    W32 = (N + 31) // 32
+    out = ["__device__ __forceinline__ void body(const v2s *__restrict__ A, const uint32_t *__restrict__ SL, "
+           "const uint32_t *__restrict__ SH, v2s *__restrict__ T)", "{"]
+    for j in range(M):
+        cols = [int(c) for c in np.nonzero(H[j])[0]]
+        masks = [0] * W32
+        for c in cols:
+            masks[c // 32] |= 1 << (c % 32)
+        cl = " + ".join("__builtin_popcount(SL[%d] & 0x%08xu)" % (k, masks[k]) for k in range(W32) if masks[k])
+        ch = " + ".join("__builtin_popcount(SH[%d] & 0x%08xu)" % (k, masks[k]) for k in range(W32) if masks[k])
+        out.append("    { // row %d" % j)
+        out.append("        const uint32_t cl = %s, ch = %s;" % (cl, ch))
+        out.append("        const v2s sg = __builtin_bit_cast(v2s, ((cl & 1u) ? 0xffffu : 1u) | "
+                   "(((ch & 1u) ? 0xffffu : 1u) << 16));")
+        # min1 <= min2 of the row: two running chains over alternate entries,
+        # emitted interleaved (independent, so their dependent min / max steps
+        # overlap), then one merge (x1, x2), (y1, y2) -> (min(x1, y1),
+        # min(max(x1, y1), min(x2, y2))): the same instruction count as one chain
+        ca, cb = cols[0::2], cols[1::2]
+
+        def start(ch, tag):
+            if len(ch) >= 2:
+                return ["v2s %s1 = vmin(A[%d], A[%d]), %s2 = vmax(A[%d], A[%d]);" % (tag, ch[0], ch[1], tag, ch[0], ch[1])], ch[2:]
+            return ["v2s %s1 = A[%d], %s2 = (v2s)127;" % (tag, ch[0], tag)], ch[1:]
+        la, ra = start(ca, "x")
+        lb, rb = start(cb, "y")
+        out.append("        " + la[0] + " " + lb[0])
+        for k in range(max(len(ra), len(rb))):
+            parts = []
+            if k < len(ra):
+                parts.append("x2 = vmax(x1, vmin(x2, A[%d])); x1 = vmin(x1, A[%d]);" % (ra[k], ra[k]))
+            if k < len(rb):
+                parts.append("y2 = vmax(y1, vmin(y2, A[%d])); y1 = vmin(y1, A[%d]);" % (rb[k], rb[k]))
+            out.append("        " + " ".join(parts))
+        out.append("        const v2s m1 = vmin(x1, y1), m2 = vmin(vmax(x1, y1), vmin(x2, y2));")
+        out.append("        const v2s q1 = (m1 * (v2s)3 + (v2s)2) >> (v2s)2, q2 = (m2 * (v2s)3 + (v2s)2) >> (v2s)2;")
+        out.append("        const v2s K = m1 * (v2s)100 + q2;")
+        for c in cols:
+            out.append("        T[%d] = sg * vmax(q1, vmin(q2, A[%d] * (v2s)(-100) + K)) + T[%d];" % (c, c, c))
+        out.append("    }")
+    out.append("}")
+    return "\n".join(out)
+
+
 def syndrome_source(Hs: np.ndarray) -> str:
     Ms, N = Hs.shape
     W64 = (N + 63) // 64
@@ -209,18 +271,26 @@ def generate(stage1_lib: str, out_dir: str):
     entries = []
     decls = []
     mats = {}
-    for (name, rows, B, mode, prec, waves) in SPECS:
+    for spec in SPECS:
+        name, rows, B, mode, prec, waves = spec[:6]
+        variant = spec[6] if len(spec) > 6 else 0
         if (name, rows) not in mats:
             mats[(name, rows)] = _matrices(lib, name, rows)
         H, Hs = mats[(name, rows)]
         M, N = H.shape
-        ns = "spec_%s_m%d_b%d%s" % (name, M, B, "_fix8" if prec else "")
+        ns = "spec_%s_m%d_b%d%s%s" % (name, M, B, "_fix8" if prec else "", "_pk16" if variant else "")
         body_path = os.path.join(out_dir, ns + "_body.inc")
         regacc = 1 if N <= 64 and B > 1 else 0
+        pk16 = 1 if prec and regacc and variant else 0
+        if variant and not pk16:
+            raise ValueError("the packed variant needs N <= 64, fixed point and 3 or 9 branches")
         with open(body_path, "w") as fh:
             fh.write("// generated: %s, H_o %d x %d, %d edges\n" % (name, M, N, int(H.sum())))
-            fh.write((body_source_fix8(H, regacc) if prec else body_source(H, regacc)) + "\n\n" +
-                     syndrome_source(Hs) + "\n")
+            if pk16:
+                fh.write(body_source_pk16(H, B))
+            else:
+                fh.write(body_source_fix8(H, regacc) if prec else body_source(H, regacc))
+            fh.write("\n\n" + syndrome_source(Hs) + "\n")
         src_path = os.path.join(out_dir, ns + ".hip")
         with open(src_path, "w") as fh:
             fh.write('#include "spec_launch.h"\n')
@@ -229,11 +299,12 @@ def generate(stage1_lib: str, out_dir: str):
                      "#define SPEC_Y_GLOBAL %d\n#define SPEC_FIX8 %d\n#define SPEC_REGACC %d\n"
                      % (N, B, ns, waves, yg, prec, regacc))
             fh.write('#define SPEC_BODY "%s"\n' % os.path.basename(body_path))
-            fh.write('#include "nms_spec_fp32.inc"\n')
+            fh.write('#include "%s"\n' % ("nms_spec_pk16.inc" if pk16 else "nms_spec_fp32.inc"))
         srcs.append(src_path)
         decls.append("namespace %s { hipError_t launch(const SpecLaunch &, int, int, hipStream_t); }" % ns)
-        entries.append("    {0x%016xull, %d, %d, %d, %d, %d, %d, %d, \"%s\", &%s::launch}," %
-                       (fingerprint(H), N, M, B, mode, prec, waves, 1 if N > 64 else 0, ns, ns))
+        entries.append("    {0x%016xull, %d, %d, %d, %d, %d, %d, %d, %d, %d, \"%s\", &%s::launch}," %
+                       (fingerprint(H), N, M, B, mode, prec, variant, waves, 1 if N > 64 else 0,
+                        128 if pk16 else 64, ns, ns))
     table = "\n".join(decls) + "\nstatic const SpecKernel kSpecKernels[] = {\n" + "\n".join(entries) + \
-        "\n    {0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n"
+        "\n    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n"
     return srcs, table

@@ -9,10 +9,14 @@ arrival order up to the slot's frame capacity (admission by memory: a slot
 never holds more than it was sized for) and the whole batch is decoded in one
 mixed-code call; slots run on their own streams, so the batch of a newly
 admitted request overlaps on the device with the batches already in flight.
-When a slot's results are back, frames whose syndrome is still nonzero are
-handed to a pool of host threads running order-p OSD on the channel LLRs (the
-hybrid of Section II-B and the complexity account C_t = C_1 + F_1 C_2 of
-Section IV); a request completes when all of its frames have a decision.
+Frames whose syndrome is still nonzero go to order-p OSD on their channel
+LLRs (the hybrid of Section II-B and the complexity account C_t = C_1 +
+F_1 C_2 of Section IV), either on the device, enqueued on the slot's stream
+right after the decode (osd_on="device"), or on the host when the slot's
+results are back (osd_on="host": one library call per code present in the
+slot, spread over the OSD threads inside the library, so the interpreter lock
+is taken once per call rather than per frame).  A request completes when all
+of its frames have a decision.
 
 Every frame decodes exactly as it would alone: the kernel's arithmetic for a
 frame depends only on that frame's LLRs and offset, and OSD is deterministic.
@@ -46,7 +50,6 @@ class Request:
     t_gpu: float = 0.0
     t_done: float = 0.0
     n_osd: int = 0
-    _osd_left: int = 0
 
     @property
     def frames(self) -> int:
@@ -77,12 +80,14 @@ class _Slot:
 class Engine:
     """codes: [(name, rows of H_o)].  slot_frames: capacity of one slot (at
     least the largest request).  osd_order: order of the host OSD stage (None
-    disables the hybrid); a request's failed frames are split into chunks of
-    osd_chunk frames spread over osd_workers host threads.  tuned: apply the
+    disables the hybrid), run on the device (osd_on="device") or on the host
+    (osd_on="host": each finished slot's failed frames go to one OSD call per
+    code, spread over osd_threads native threads; calls run one at a time on
+    a helper thread, so the scheduler never waits for them).  tuned: apply the
     autotuner's cached launch shapes."""
 
-    def __init__(self, codes, slot_frames=1 << 16, n_slots=3, osd_order=2, osd_workers=8,
-                 precision=B.FP32, max_iter=8, tuned=True, device="cuda", osd_chunk=16):
+    def __init__(self, codes, slot_frames=1 << 16, n_slots=3, osd_order=2, osd_on="device", osd_threads=8,
+                 precision=B.FP32, max_iter=8, tuned=True, device="cuda"):
         import torch
         self.torch = torch
         self.dev = torch.device(device)
@@ -107,10 +112,13 @@ class Engine:
         self._mixes = {}
         self.cap = slot_frames
         self.ld = self.mix.ld
+        if osd_on not in ("device", "host"):
+            raise B.BchError("osd_on must be 'device' or 'host'")
         self.osd_order = osd_order
-        self.osd_chunk = osd_chunk
+        self.osd_on = osd_on
+        self.osd_threads = osd_threads
         self.pending = collections.deque()
-        self.osd_pool = ThreadPoolExecutor(osd_workers) if osd_order is not None else None
+        self.osd_pool = ThreadPoolExecutor(1) if osd_order is not None and osd_on == "host" else None
         self.osd_jobs = []
         ws_bytes = max(1, self.mix.workspace_size(slot_frames))
         self.slots = []
@@ -161,10 +169,8 @@ class Engine:
             still = []
             for fut, req in self.osd_jobs:
                 if fut.done():
-                    req.t_done = max(req.t_done, fut.result())
-                    req._osd_left -= 1
-                    if req._osd_left == 0:
-                        done.append(req)
+                    req.t_done = fut.result()
+                    done.append(req)
                 else:
                     still.append((fut, req))
             self.osd_jobs = still
@@ -175,11 +181,12 @@ class Engine:
                 self._launch(s)
         return done
 
-    def drain(self, sleep=0.0):
+    def drain(self, sleep=20e-6):
         out = []
         while self.busy():
-            out += self.poll()
-            if sleep:
+            new = self.poll()
+            out += new
+            if not new and sleep:
                 time.sleep(sleep)
         return out
 
@@ -206,8 +213,12 @@ class Engine:
             s.d_llr[:n].copy_(s.h_llr[:n], non_blocking=True)
             s.d_ci[:n].copy_(s.h_ci[:n], non_blocking=True)
             s.d_do[:n].copy_(s.h_do[:n], non_blocking=True)
-            self._mix(present).decode_into(s.d_ci[:n], s.d_llr[:n], s.d_do[:n], s.d_bits[:n], s.d_iters[:n],
-                                           s.d_flags[:n], s.ws, stream=s.stream)
+            mix = self._mix(present)
+            mix.decode_into(s.d_ci[:n], s.d_llr[:n], s.d_do[:n], s.d_bits[:n], s.d_iters[:n], s.d_flags[:n], s.ws,
+                            stream=s.stream)
+            if self.osd_order is not None and self.osd_on == "device":
+                mix.osd_into(s.d_ci[:n], s.d_llr[:n], self.osd_order, s.d_bits[:n], skip=s.d_flags[:n],
+                             stream=s.stream)
             s.h_bits[:n].copy_(s.d_bits[:n], non_blocking=True)
             s.h_iters[:n].copy_(s.d_iters[:n], non_blocking=True)
             s.h_flags[:n].copy_(s.d_flags[:n], non_blocking=True)
@@ -240,6 +251,7 @@ class Engine:
         now = time.perf_counter()
         hb = s.h_bits.numpy().view(np.uint64)
         hi, hf = s.h_iters.numpy(), s.h_flags.numpy()
+        by_code = {}
         for r, off in s.members:
             F = r.frames
             W = self.decs[r.code].W64
@@ -250,25 +262,34 @@ class Engine:
             r.t_gpu = now
             failed = np.nonzero(r.flags == 0)[0]
             r.n_osd = int(failed.size)
-            if r.n_osd and self.osd_pool is not None:
-                chunks = [failed[k:k + self.osd_chunk] for k in range(0, failed.size, self.osd_chunk)]
-                r._osd_left = len(chunks)
-                for ch in chunks:
-                    self.osd_jobs.append((self.osd_pool.submit(self._osd, r, ch), r))
+            if r.n_osd and self.osd_order is not None and self.osd_on == "device":
+                r.flags[failed] |= FLAG_OSD  # decided on the device in the same slot
+                r.t_done = now
+                done.append(r)
+            elif r.n_osd and self.osd_pool is not None:
+                by_code.setdefault(r.code, []).append((r, failed))
             else:
                 r.t_done = now
                 done.append(r)
+        for code, segs in by_code.items():
+            fut = self.osd_pool.submit(self._osd, code, segs)
+            for r, _ in segs:
+                self.osd_jobs.append((fut, r))
         s.members = []
         s.busy = False
         return done
 
-    def _osd(self, r: Request, idx: np.ndarray) -> float:
-        """OSD of some of a request's failed frames (one host thread);
-        returns the completion time."""
-        code = self.codes[r.code][0]
-        out = B.osd_decode(code, r.llr[idx], self.osd_order, n_threads=1)
-        r.bits[idx, :out.shape[1]] = out
-        r.flags[idx] |= FLAG_OSD
+    def _osd(self, code: int, segs) -> float:
+        """OSD of the failed frames of several requests of one code, in one
+        library call over osd_threads native threads; returns the
+        completion time."""
+        llr = np.concatenate([r.llr[idx] for r, idx in segs])
+        out = B.osd_decode(self.codes[code][0], llr, self.osd_order, n_threads=self.osd_threads)
+        k = 0
+        for r, idx in segs:
+            r.bits[idx, :out.shape[1]] = out[k:k + idx.size]
+            r.flags[idx] |= FLAG_OSD
+            k += idx.size
         return time.perf_counter()
 
     def close(self):
@@ -309,14 +330,17 @@ def run_trace(engine: Engine, reqs, offsets):
     max_busy = 0
     while k < len(order) or engine.busy():
         now = time.perf_counter() - t0
+        k0 = k
         while k < len(order) and offsets[order[k]] <= now:
             r = reqs[order[k]]
             r.arrival = t0 + offsets[order[k]]
             engine.submit(r)
             k += 1
-        done += engine.poll()
+        new = engine.poll()
+        done += new
         max_busy = max(max_busy, sum(s.busy for s in engine.slots))
-        time.sleep(0)  # let the OSD threads take the interpreter lock
+        if not new and k == k0:
+            time.sleep(20e-6)  # idle: release the interpreter lock to the OSD helper
     wall = max(r.t_done for r in done) - t0
     engine.max_busy_slots = max_busy
     return done, wall

@@ -3,8 +3,9 @@
 Every test decodes the same seeded synthetic frames with the C-ABI library on
 the GPU and with the FP64 oracle on the CPU, and applies the bar of
 tests/helpers.compare_with_oracle: identical decoded words, iteration counts and
-convergence flags on all frames but ties, per-iteration posteriors within 1e-5
-(normwise) of the oracle."""
+convergence flags on all frames but ties, and every iteration's posterior within
+1e-5 (normwise) of the oracle's: in restart mode, of one oracle iteration from the
+GPU's own previous iterate; in the edge-memory modes, of the oracle's trajectory."""
 import numpy as np
 import pytest
 
@@ -45,6 +46,7 @@ def run_pair(B, name, rows, F, ebn0, seed, n_branches, mode, max_iter, alpha=0.7
     words = B.unpack_bits(bits.cpu().numpy().view(np.uint64), c.N)
     res = oracle.decode_batch(H, oc.Hstd, fr.llr, fr.d_o, n_branches, alpha, max_iter, mode,
                               threads=8, trace=True)
+    dec.onestep = (H, oc.Hstd, fr.llr, fr.d_o, n_branches, alpha) if mode == oracle.R1 else None
     return fr, (words, iters.cpu().numpy(), flg.cpu().numpy(), tr.cpu().numpy()), res, dec
 
 
@@ -56,14 +58,14 @@ def test_enhanced_nms_restart_mode(B, name, ebn0, generic):
     fr, g, o, dec = run_pair(B, name, HO_ROWS[name], F, ebn0, 11, 9, oracle.R1, 8,
                              flags=B.FORCE_GENERIC if generic else 0)
     assert dec.specialized == (not generic)
-    compare_with_oracle(*g, *o)
+    compare_with_oracle(*g, *o, onestep=dec.onestep)
 
 
 @pytest.mark.parametrize("F", [1, 2, 63, 64, 65, 300])
 def test_specialised_small_and_ragged_batches(B, F):
     fr, g, o, dec = run_pair(B, "bch63_45", 33, F, 2.0, 30 + F, 9, oracle.R1, 8)
     assert dec.specialized
-    compare_with_oracle(*g, *o)
+    compare_with_oracle(*g, *o, onestep=dec.onestep)
 
 
 @pytest.mark.parametrize("name,rows,F,ebn0", [("bch63_45", 33, 1_000_000, 3.0),
@@ -122,10 +124,17 @@ def test_plain_nms_standard_matrix_config(B):
     assert abs(fer_g - fer_o) <= 0.005
 
 
-def test_three_branch_variant(B):
-    F = 200
-    fr, g, o, _ = run_pair(B, "bch63_45", 33, F, 3.0, 13, 3, oracle.R1, 8)
-    compare_with_oracle(*g, *o)
+@pytest.mark.parametrize("generic", [False, True])
+@pytest.mark.parametrize("name,nb", [("bch63_45", 3), ("bch63_36", 3), ("bch63_45", 1), ("bch63_36", 1)])
+def test_one_and_three_branch_variants(B, name, nb, generic):
+    """Restart mode with 3 branches (the three shifts of y) and with 1 (NMS on
+    H_o alone): the specialised kernels of the branch-count ablation and the
+    generic kernel, against the oracle."""
+    F = 64 * 3 + 9
+    fr, g, o, dec = run_pair(B, name, HO_ROWS[name], F, 3.0, 13, nb, oracle.R1, 8,
+                             flags=B.FORCE_GENERIC if generic else 0)
+    assert dec.specialized == (not generic)
+    compare_with_oracle(*g, *o, onestep=dec.onestep)
 
 
 def test_edge_cases(B):
@@ -199,7 +208,7 @@ def test_results_independent_of_batch_composition(B):
 
 
 # ------------------------------------------------------------ fixed point
-def run_fix8_pair(B, name, rows, F, ebn0, seed, scale=4.0):
+def run_fix8_pair(B, name, rows, F, ebn0, seed, scale=4.0, flags=0):
     c, p = lib_objects(B, name, rows)
     oc = oracle_code(name)
     H = oracle_hopt(name, rows)
@@ -207,7 +216,7 @@ def run_fix8_pair(B, name, rows, F, ebn0, seed, scale=4.0):
     llr = torch.from_numpy(fr.llr).cuda()
     q = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
     B.quantize_llr(llr, c.N, scale, q)
-    dec = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, max_iter=8, precision=B.FIX8)
+    dec = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, max_iter=8, precision=B.FIX8, flags=flags)
     assert dec.specialized
     d_o = torch.from_numpy(fr.d_o).cuda()
     bits, iters, flg, tr = dec.decode(q, d_o, trace=True)
@@ -219,14 +228,17 @@ def run_fix8_pair(B, name, rows, F, ebn0, seed, scale=4.0):
     return fr, words, iters.cpu().numpy(), flg.cpu().numpy(), tr.cpu().numpy(), oc_, oit, ocv, otr
 
 
-@pytest.mark.parametrize("name,ebn0", [("bch63_45", 3.0), ("bch63_36", 3.5), ("bch127_99", 4.0),
-                                       ("bch127_64", 3.5)])
-def test_fixed_point_bit_exact(B, name, ebn0):
+@pytest.mark.parametrize("name,ebn0,packed", [("bch63_45", 3.0, False), ("bch63_36", 3.5, False),
+                                              ("bch63_45", 3.0, True), ("bch63_36", 3.5, True),
+                                              ("bch127_99", 4.0, False), ("bch127_64", 3.5, False)])
+def test_fixed_point_bit_exact(B, name, ebn0, packed):
     """int8 messages, (3m+2)>>2 c2v magnitudes, integer branch average:
     identical decoded words, iteration counts, flags and every per-iteration
-    posterior as the integer oracle, on every frame."""
-    F = 64 * 5 + 17
-    fr, w, it, fl, tr, ow, oit, ocv, otr = run_fix8_pair(B, name, HO_ROWS[name], F, ebn0, 41)
+    posterior as the integer oracle, on every frame (also for the packed
+    16-bit kernel, two frames per lane)."""
+    F = 128 * 3 + 17
+    fr, w, it, fl, tr, ow, oit, ocv, otr = run_fix8_pair(B, name, HO_ROWS[name], F, ebn0, 41,
+                                                         flags=B.PACKED16 if packed else 0)
     assert np.array_equal(w, ow)
     assert np.array_equal(it, oit)
     assert np.array_equal(fl.astype(bool), ocv)
@@ -397,3 +409,49 @@ def test_mixed_batch_graph_replay(B):
         eb, ei, ef = mix.decode(ci, llr, d_o)
         torch.cuda.synchronize()
         assert torch.equal(bits, eb) and torch.equal(iters, ei) and torch.equal(flg, ef), rep
+
+
+# ------------------------------------------------------------ device OSD
+@pytest.mark.parametrize("name", ["bch63_36", "bch63_45", "bch127_64", "bch127_78", "bch127_99"])
+def test_device_osd_matches_oracle(B, name):
+    """Device OSD-p (p = 0, 1, 2) equals the oracle's OSD bit for bit, on
+    noisy frames and on integer-valued LLRs (equal reliabilities: ties in the
+    ordering and in the candidate costs)."""
+    c, p = lib_objects(B, name, 0)
+    dec = B.Decoder(c, p, n_branches=1, mode=B.MODE_EXTRINSIC, max_iter=4)
+    oc = oracle_code(name)
+    fr = synth.frames(name, 200, 1.5, seed=61)
+    tied = np.round(fr.llr[:100] / 3.0).astype(np.float32)  # many |L| equal
+    tied[:, oc.N:] = 0.0
+    llr_h = np.concatenate([fr.llr, tied])
+    llr_h[5] = 0.0  # all-zero frame: every candidate costs 0
+    llr = torch.from_numpy(llr_h).cuda()
+    for order in (0, 1, 2):
+        bits = torch.zeros((llr_h.shape[0], dec.W64), dtype=torch.int64, device="cuda")
+        dec.osd_into(llr, order, bits)
+        torch.cuda.synchronize()
+        got = B.unpack_bits(bits.cpu().numpy().view(np.uint64), oc.N)
+        ref = oracle.osd_batch(oc.G, llr_h, order)
+        assert np.array_equal(got, ref), (order, np.nonzero((got != ref).any(1))[0][:10])
+
+
+def test_device_osd_skip_and_hybrid(B):
+    """Frames with skip set are untouched; NMS followed by device OSD on the
+    frames whose syndrome stayed nonzero equals the host hybrid."""
+    name, rows = "bch127_64", 72
+    c, p = lib_objects(B, name, rows)
+    dec = B.Decoder(c, p, n_branches=9, max_iter=8)
+    fr = synth.frames(name, 700, 2.5, seed=62)
+    llr = torch.from_numpy(fr.llr).cuda()
+    d_o = torch.from_numpy(fr.d_o).cuda()
+    bits, iters, flg, _ = dec.decode(llr, d_o)
+    nms = bits.clone()
+    dec.osd_into(llr, 2, bits, skip=flg)
+    torch.cuda.synchronize()
+    fl = flg.cpu().numpy()
+    assert (fl == 0).sum() > 20
+    b_dev = bits.cpu().numpy().view(np.uint64)
+    conv = fl != 0
+    assert np.array_equal(b_dev[conv], nms.cpu().numpy().view(np.uint64)[conv])  # skipped frames untouched
+    host = B.osd_decode(c, fr.llr, 2, skip=fl.astype(np.uint8), bits=nms.cpu().numpy().view(np.uint64).copy())
+    assert np.array_equal(b_dev, host)

@@ -42,11 +42,13 @@ def packed(cw):
     return np.packbits(p, axis=1, bitorder="little").view(np.uint64)
 
 
-def test_served_results_equal_alone(S):
+@pytest.mark.parametrize("osd_on", ["device", "host"])
+def test_served_results_equal_alone(S, osd_on):
     """Requests arriving at 20,000/s (several in flight on separate slots):
     every frame's decision, iteration count and flags equal those of the
-    request decoded alone (its code's decoder, then OSD-2 on its failures)."""
-    eng = S.Engine(SERVE_CODES, slot_frames=8192, n_slots=3, osd_order=2, osd_workers=4)
+    request decoded alone (its code's decoder, then host OSD-2 on its
+    failures), with the service's OSD stage on the device or on the host."""
+    eng = S.Engine(SERVE_CODES, slot_frames=8192, n_slots=3, osd_order=2, osd_on=osd_on, osd_threads=4)
     tr, reqs, cws = make_requests(S, 48, 7)
     done, wall = S.run_trace(eng, reqs, [d.t / 20000.0 for d in tr])
     assert len(done) == len(reqs) and eng.launches >= 2
@@ -65,7 +67,7 @@ def test_served_results_equal_alone(S):
 def test_hybrid_decisions(S):
     """OSD-2 outputs are codewords and equal the oracle's OSD-2 on the same
     channel LLRs; the hybrid's frame errors are at most the NMS stage's."""
-    eng = S.Engine(SERVE_CODES, slot_frames=8192, n_slots=2, osd_order=2, osd_workers=4)
+    eng = S.Engine(SERVE_CODES, slot_frames=8192, n_slots=2, osd_order=2, osd_threads=4)
     tr, reqs, cws = make_requests(S, 24, 11, max_log2=10)
     for r in reqs:
         eng.submit(r)
