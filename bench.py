@@ -65,10 +65,10 @@ FIX_SCALE = 4.0
 # x 1.0).  It holds only for the kernel sources the counters were taken on
 # (hash of the kernel template, its launch header and the row-function
 # generator); any other build reports traffic null.
-TRAFFIC_SRC_HASH = "c54594ebebd46184"
+TRAFFIC_SRC_HASH = "3328c51123600d2f"
 TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written) bytes per frame
-    "spec_bch63_36_m122_b9": (302.09, 182.74),
-    "spec_bch63_45_m33_b9": (263.70, 53.87),
+    "spec_bch63_36_m122_b9": (382.07, 492.75),
+    "spec_bch63_45_m33_b9": (265.08, 53.23),
 }
 
 
@@ -121,7 +121,10 @@ class Item:
     """One launch of the timed step: a single-code decode or a mixed-code one."""
 
     def __init__(self, label, prec, frames, launch):
-        self.label, self.prec, self.frames, self.launch = label, prec, frames, launch
+        self.label, self.prec, self.frames = label, prec, frames
+        self.launch_on = launch          # (stream) -> enqueue the launch on that stream
+        self.launch = lambda: launch()   # on the decode stream
+        self.graph = None
         self.kernel = "mixed"
         self.stats = None     # () -> (per-point dicts, algorithmic ops, information bits)
         self.sample = None    # () -> [(code name, llr rows, d_o, gpu words, gpu iters)] for the CPU leg
@@ -186,8 +189,8 @@ def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_ba
                 fl = torch.empty(F, dtype=torch.uint8, device=dev)
                 ws = torch.empty(max(1, dec.workspace_size(F)), dtype=torch.uint8, device=dev)
                 item = Item("%s@%g" % (name, e), prec, F,
-                            lambda dec=dec, inp=inp, d_o_d=d_o_d, bits=bits, it=it, fl=fl, ws=ws:
-                            dec.decode_into(inp, d_o_d, bits, it, fl, workspace=ws, stream=stream))
+                            lambda st=stream, dec=dec, inp=inp, d_o_d=d_o_d, bits=bits, it=it, fl=fl, ws=ws:
+                            dec.decode_into(inp, d_o_d, bits, it, fl, workspace=ws, stream=st))
                 item.inputs, item.outputs = (inp, d_o_d), (bits, it, fl)
                 item.kernel = ("spec_%s_m%d_b9%s" % (name, pcm.M, "_fix8" if prec == "fix8" else "")
                                if dec.specialized else "generic_%s" % prec)
@@ -249,8 +252,8 @@ def build_mixed(args, B, torch, dev, stream, codes, probs, lohi, precisions, see
         it = torch.zeros(F, dtype=torch.uint8, device=dev)
         fl = torch.zeros(F, dtype=torch.uint8, device=dev)
         ws = torch.empty(max(1, mix.workspace_size(F)), dtype=torch.uint8, device=dev)
-        item = Item("mixed", prec, F, lambda mix=mix, inp=inp, bits=bits, it=it, fl=fl, ws=ws:
-                    mix.decode_into(ci_d, inp, d_o_d, bits, it, fl, ws, stream=stream))
+        item = Item("mixed", prec, F, lambda st=stream, mix=mix, inp=inp, bits=bits, it=it, fl=fl, ws=ws:
+                    mix.decode_into(ci_d, inp, d_o_d, bits, it, fl, ws, stream=st))
 
         def stats(prec=prec, bits=bits, it=it, fl=fl):
             w = bits.cpu().numpy().view(np.uint64)
@@ -504,6 +507,8 @@ def main():
     ap.add_argument("--precision", default="", choices=["", "fp32", "fix8", "both"],
                     help="override the workload's precisions")
     ap.add_argument("--packed16", action="store_true", help="fixed point: the packed 16-bit kernels (N = 63)")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture each launch of the step in a HIP graph once and replay it in the timed loop")
     ap.add_argument("--requests", type=int, default=3000, help="requests of the serving workload")
     ap.add_argument("--osd", default="device", choices=["device", "host"], help="serving: where OSD-2 runs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -557,17 +562,35 @@ def main():
     gen_s = time.time() - t0
     total_frames = sum(it.frames for it in items)
 
+    for _ in range(args.warmup):
+        for item in items:
+            item.launch()
+    torch.cuda.synchronize()
+    if args.graph:
+        # one graph per launch (prepass and persistent kernels of every code),
+        # captured on a side stream and replayed on the decode stream
+        cap = torch.cuda.Stream()
+        for item in items:
+            g = torch.cuda.CUDAGraph()
+            cap.wait_stream(stream)
+            with torch.cuda.stream(cap):
+                with torch.cuda.graph(g, stream=cap):
+                    item.launch_on(cap)
+            stream.wait_stream(cap)
+            item.graph = g
+        torch.cuda.synchronize()
+
     def step(events=None):
         for k, item in enumerate(items):
             if events is not None:
                 events[k][0].record(stream)
-            item.launch()
+            if args.graph:
+                item.graph.replay()
+            else:
+                item.launch()
             if events is not None:
                 events[k][1].record(stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in items]
           for _ in range(args.steps)]
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -625,8 +648,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if precisions == ["fp32"] else "f32+i8",
         "data": "synthetic",
-        "config": {"workload": "%s, %d frames per %s, Eb/N0 %s dB" % (
-                       wdesc, args.frames, "step" if args.workload == "mixed" else "point", ebn0_desc),
+        "config": {"workload": "%s, %d frames per %s, Eb/N0 %s dB%s" % (
+                       wdesc, args.frames, "step" if args.workload == "mixed" else "point", ebn0_desc,
+                       ", each launch replayed from a captured HIP graph" if args.graph else ""),
                    "frames_per_step": total_frames},
         "frames_per_s_by_precision": {p: frames_by_prec[p] / time_by_prec[p] for p in time_by_prec},
         "info_gbit_s": info_bits * args.steps / elapsed / 1e9,
