@@ -51,36 +51,33 @@ __global__ void __launch_bounds__(TPB) bucket_count(const uint8_t *__restrict__ 
 __global__ void __launch_bounds__(SCAN) bucket_scan(int *__restrict__ blk_hist, int nblk, int dp,
                                                     int range_frames, BucketWs w)
 {
-    __shared__ int part[SCAN];
     __shared__ int bucket_total[MAXB];
     __shared__ int bucket_start[MAXB];
     __shared__ int range_start[MAXB + 1];
     const int tid = threadIdx.x;
-    // each thread owns a contiguous chunk of blocks
-    const int per = (nblk + SCAN - 1) / SCAN;
-    const int lo = tid * per, hi = min(nblk, lo + per);
-    for (int d = 0; d < dp; d++) {
-        int s = 0;
-        for (int b = lo; b < hi; b++)
-            s += blk_hist[(size_t)b * dp + d];
-        part[tid] = s;
-        __syncthreads();
-        for (int off = 1; off < SCAN; off <<= 1) {  // inclusive scan
-            const int v = tid >= off ? part[tid - off] : 0;
-            __syncthreads();
-            part[tid] += v;
-            __syncthreads();
+    // one wave per bucket: exclusive prefix over the blocks, 64 blocks at a
+    // time with a shuffle scan (no workgroup barriers inside)
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int d = wave; d < dp; d += SCAN / 64) {
+        int carry = 0;
+        for (int b0 = 0; b0 < nblk; b0 += 64) {
+            const int b = b0 + lane;
+            const int c = b < nblk ? blk_hist[(size_t)b * dp + d] : 0;
+            int v = c;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(v, off);
+                if (lane >= off)
+                    v += t;
+            }
+            if (b < nblk)
+                blk_hist[(size_t)b * dp + d] = carry + v - c;  // offset inside the bucket
+            carry += __shfl(v, 63);
         }
-        int run = part[tid] - s;  // exclusive prefix of this thread's chunk
-        for (int b = lo; b < hi; b++) {
-            const int c = blk_hist[(size_t)b * dp + d];
-            blk_hist[(size_t)b * dp + d] = run;  // offset inside the bucket
-            run += c;
-        }
-        if (tid == SCAN - 1)
-            bucket_total[d] = part[tid];
-        __syncthreads();
+        if (lane == 0)
+            bucket_total[d] = carry;
     }
+    __syncthreads();
     if (tid == 0) {
         int start = 0, nr = 0;
         for (int d = 0; d < dp; d++) {
