@@ -289,9 +289,10 @@ SERVE_LOADS = [0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2]
 def run_serve(args):
     """Serving workload: Poisson arrivals of requests of round(2^(12U))
     frames, code uniform over four, Eb/N0 U[2, 5] dB per request; continuous
-    batching on the GPU, OSD-2 on the host for frames the NMS stage leaves
-    with a nonzero syndrome.  Saturation is measured with every request
-    submitted at once; the offered load is then swept over fractions of it."""
+    batching on the GPU, OSD-2 (on the device, or on the host with --osd host)
+    for frames the NMS stage leaves with a nonzero syndrome.  Saturation is
+    measured with every request submitted at once; the offered load is then
+    swept over fractions of it."""
     import torch
 
     from paper_2412_20828_amd import serving
@@ -319,6 +320,7 @@ def run_serve(args):
     fer_h = np.mean(np.concatenate([(r.bits != pack(truth[r.rid])).any(1) for r in done]))
     fer_n = np.mean(np.concatenate([((r.flags & serving.FLAG_OSD) != 0) | (r.bits != pack(truth[r.rid])).any(1)
                                     for r in done]))
+    osd_cost = osd_costs(eng, done, torch)
     loads = []
     for frac in SERVE_LOADS:
         rate = frac * sat["frames_per_s"] / mean_frames
@@ -349,6 +351,7 @@ def run_serve(args):
                        "request_p99_at_saturation": sat["latency_ms_p99"]},
         "fer_hybrid": float(fer_h), "fer_nms_only": float(fer_n),
         "load_sweep": loads,
+        "osd_us_per_frame": osd_cost,
         "max_sustained_frames_per_s": max([r["frames_per_s"] for r in ok], default=None),
         "roofline": None,
         "input_generation_s": gen_s,
@@ -451,6 +454,34 @@ def run_experiment(args):
     print(json.dumps(out))
 
 
+def osd_costs(eng, done, torch, cap=2000):
+    """Per failed frame: the library's host OSD-2 on one thread, and the
+    device OSD-2 (throughput of one launch over the same frames), per code."""
+    from paper_2412_20828_amd import binding as B
+    from paper_2412_20828_amd import serving
+    out = {}
+    for k, (code, _) in enumerate(eng.codes):
+        rows = [r.llr[np.nonzero(r.flags & serving.FLAG_OSD)[0]] for r in done if r.code == k and r.n_osd]
+        if not rows:
+            continue
+        llr = np.ascontiguousarray(np.concatenate(rows)[:cap])
+        n = llr.shape[0]
+        t0 = time.time()
+        B.osd_decode(code, llr, 2, n_threads=1)
+        host = (time.time() - t0) / n * 1e6
+        dl = torch.from_numpy(llr).cuda()
+        bits = torch.zeros((n, 2), dtype=torch.int64, device="cuda")
+        dec = eng.decs[k]
+        dec.osd_into(dl, 2, bits)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dec.osd_into(dl, 2, bits)
+        b.record()
+        torch.cuda.synchronize()
+        out[eng.names[k]] = {"frames": n, "host_one_thread_us": host, "device_us": a.elapsed_time(b) * 1e3 / n}
+    return out
+
+
 def cpu_hybrid_baseline(eng, tr, frs, names, budget_s, gpu_fps):
     """The oracle's hybrid (FP64 enhanced NMS, then OSD-2 on the frames whose
     syndrome is nonzero) on a bounded sample of the requests' frames."""
@@ -458,9 +489,9 @@ def cpu_hybrid_baseline(eng, tr, frs, names, budget_s, gpu_fps):
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     mats = {}
     for name, (code, pcm) in zip(names, eng.codes):
+        H, Hstd = oracle_matrices(oracle, name, pcm)
         m, p, t = synth.CODES[name]
-        oc = oracle.Code(m, p, t)
-        mats[name] = (pcm.dense(), oc.Hstd, oc.G)
+        mats[name] = (H, Hstd, oracle.Code(m, p, t).G)
     sample = []
     for k in range(len(names)):
         ks = [i for i, d in enumerate(tr) if d.code == k][:16]
@@ -678,6 +709,17 @@ def main():
     print(json.dumps(res))
 
 
+def oracle_matrices(oracle, name, pcm):
+    """The oracle's own H_o (same construction parameters as the library's)
+    and standard H; refuses to go on if the library's H_o differs."""
+    m, p, t = synth.CODES[name]
+    oc = oracle.Code(m, p, t)
+    H, _, _ = oracle.build_hopt(oc, target_rows=pcm.M, seed=1)
+    if not np.array_equal(H, pcm.dense()):
+        raise RuntimeError("the library's H_o for %s differs from the oracle's" % name)
+    return H, oc.Hstd
+
+
 def cpu_baseline(samples, mats, budget_s, gpu_fps):
     """The FP64 oracle (as it stands) on a bounded sample of the same frames,
     on all host cores; also checks that the GPU outcomes on that sample are
@@ -686,8 +728,7 @@ def cpu_baseline(samples, mats, budget_s, gpu_fps):
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     Hs = {}
     for name in mats:
-        m, p, t = synth.CODES[name]
-        Hs[name] = (mats[name].dense(), oracle.Code(m, p, t).Hstd)
+        Hs[name] = oracle_matrices(oracle, name, mats[name])
     # pilot (every sample once) to size the repeat count to the budget
     t0 = time.time()
     for name, l0, d0, _, _ in samples:
@@ -707,10 +748,20 @@ def cpu_baseline(samples, mats, budget_s, gpu_fps):
         match += int(((gw[:, :W] == ow).all(1) & (gi == it[:per])).sum())
         total += per
     secs = time.time() - t0
+    # one core: the first sample only, repeated for about a tenth of the budget
+    name, l, d, _, _ = samples[0]
+    H, Hstd = Hs[name]
+    t1 = time.time()
+    n1 = 0
+    while time.time() - t1 < budget_s / 10:
+        oracle.decode_batch(H, Hstd, l, d, 9, 0.75, 8, oracle.R1, threads=1)
+        n1 += l.shape[0]
+    one = n1 / (time.time() - t1)
     return {"value": n / secs, "unit": "frames/s", "cores": threads, "kind": "oracle",
             "sample": "%d frames (the first 64 frames of each of %d launches' codes, %d repeats), FP64 "
                       "min1/min2 oracle, same frames as the GPU" % (n, len(samples), reps),
             "seconds": secs, "gpu_over_cpu": gpu_fps / (n / secs),
+            "one_core": {"value": one, "sample": "%d frames of %s" % (n1, name)},
             "oracle_match_fraction": match / max(1, total)}
 
 
