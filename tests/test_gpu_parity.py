@@ -455,3 +455,53 @@ def test_device_osd_skip_and_hybrid(B):
     assert np.array_equal(b_dev[conv], nms.cpu().numpy().view(np.uint64)[conv])  # skipped frames untouched
     host = B.osd_decode(c, fr.llr, 2, skip=fl.astype(np.uint8), bits=nms.cpu().numpy().view(np.uint64).copy())
     assert np.array_equal(b_dev, host)
+
+
+def test_mixed_full_size_sampled(B):
+    """The mixed workload at its full size: 16,000,000 interleaved frames in one
+    call per precision; 200 sampled frames per code against the oracle (FP64
+    with the tie rule for FP32, bit-exact for int8)."""
+    names = [n for n, _ in MIX]
+    F = 16_000_000
+    blocks = 32
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(16) as ex:
+        parts = list(ex.map(lambda k: synth.mixed_frames(names, F // blocks, 77, MIX_P, 1.5, 5.0, block=k),
+                            range(blocks)))
+    code_idx = np.concatenate([p.code_idx for p in parts])
+    d_o_h = np.concatenate([p.d_o for p in parts])
+    llr = torch.from_numpy(np.concatenate([p.llr for p in parts])).cuda()
+    ci = torch.from_numpy(code_idx).cuda()
+    d_o = torch.from_numpy(d_o_h).cuda()
+    rng = np.random.default_rng(5)
+    for precision in (0, 1):
+        objs = [lib_objects(B, n, r) for n, r in MIX]
+        decs = [B.Decoder(c, p, n_branches=9, max_iter=8, precision=precision) for c, p in objs]
+        inp = llr
+        if precision == B.FIX8:
+            inp = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
+            for k, (c, _) in enumerate(objs):
+                qk = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
+                B.quantize_llr(llr, c.N, 4.0, qk)
+                sel = ci == k
+                inp[sel] = qk[sel]
+                del qk, sel
+        bits, iters, flg = B.MixedDecoder(decs).decode(ci, inp, d_o)
+        torch.cuda.synchronize()
+        for k, (name, rows) in enumerate(MIX):
+            idx = np.sort(rng.choice(np.nonzero(code_idx == k)[0], 200, replace=False))
+            oc = oracle_code(name)
+            H = oracle_hopt(name, rows)
+            ti = torch.from_numpy(idx).cuda()
+            x = inp[ti].cpu().numpy()
+            w = B.unpack_bits(bits[ti].cpu().numpy().view(np.uint64)[:, :(oc.N + 63) // 64], oc.N)
+            it_h, fl_h = iters[ti].cpu().numpy(), flg[ti].cpu().numpy()
+            if precision == 0:
+                res = oracle.decode_batch(H, oc.Hstd, x, d_o_h[idx], 9, 0.75, 8, oracle.R1, threads=8, trace=True)
+                compare_with_oracle(w, it_h, fl_h, None, *res)
+            else:
+                ow, oit, ocv = oracle.decode_batch(H, oc.Hstd, x, d_o_h[idx], 9, 0.75, 8, oracle.R1,
+                                                   kind=oracle.KIND_FIXED, threads=8)
+                assert np.array_equal(w, ow) and np.array_equal(it_h, oit)
+                assert np.array_equal(fl_h.astype(bool), ocv)
+        del bits, iters, flg, inp
