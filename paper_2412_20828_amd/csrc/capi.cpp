@@ -148,7 +148,14 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
                      : nullptr;
     s.max_iter = d->prm.max_iter;
     s.alpha = d->prm.alpha;
-    e = d->spec->launch(s, d->n_cu, waves_of(d), stream);
+    // a batch of F frames has at most ceil(F / range) + dp ranges: no more
+    // persistent waves than that (small batches launch small grids)
+    const int64_t grid = (int64_t)d->n_cu * waves_of(d);
+    const int64_t most = (F + range - 1) / range + dp;
+    if (most < grid)
+        e = d->spec->launch(s, 1, (int)most, stream);
+    else
+        e = d->spec->launch(s, d->n_cu, waves_of(d), stream);
     return e == hipSuccess ? BCH_OK : hip_fail(e, "specialised kernel launch");
 }
 
