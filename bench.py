@@ -52,6 +52,7 @@ WORKLOADS = {
     "serve": (None, "2.0:5.0", 0, ["fp32"], "serving"),
     "alpha": (None, "", 0, ["fp32"], "alpha sweep"),
     "ablation": (None, "", 0, ["fp32"], "branch-count ablation"),
+    "beta": (None, "", 0, ["fp32"], "H_o redundancy sweep"),
     "mixed": ([("bch127_64", 72), ("bch127_99", 33), ("bch63_36", 122)], "1.5:5.0", 16_000_000, ["fp32", "fix8"],
               "mixed-code batch, per frame 50% BCH(127,64) H_o 72x127, 25% BCH(127,99) H_o 33x127, "
               "25% BCH(63,36) H_o 122x63 in one call, enhanced NMS 9 branches, restart mode, max 8 iterations, "
@@ -390,6 +391,11 @@ def run_experiment(args):
     9 branches, restart mode, I_m = 8, 10^6 frames per point; the argmin
     stands in for the paper's trained, unprinted values.
 
+    beta: the redundancy factor of H_o (step 5 of Section III-A): rows, edges,
+    length-4 cycles, FER and frames/s for beta in {1, 2, 4, 8, 20} for (63,36)
+    at 3 dB and {1, 2, 3} for (127,78) at 4 dB (matrices without a specialised
+    kernel run on the generic one, which the row marks).
+
     ablation: what the automorphism merge buys: plain flooding NMS on the
     standard H (one branch, extrinsic messages), NMS on H_o (one branch,
     restart mode), and the 3- and 9-branch enhanced decoders, at 2, 3 and
@@ -425,6 +431,25 @@ def run_experiment(args):
                          "fer_at_0.75": fers[alphas.index(0.75)]})
         out.update({"workload": "alpha", "config": {"workload": "alpha sweep 0.50:0.05:1.00, 9 branches, restart "
                                                                "mode, I_m 8, %d frames per point" % F}})
+    elif args.workload == "beta":
+        # H_o redundancy: M_o = M_r1 + beta (M - M_r1) rows (step 5 of Section III-A)
+        for ci, (name, betas, ebn0) in enumerate([("bch63_36", [1, 2, 4, 8, 20], 3.0),
+                                                  ("bch127_78", [1, 2, 3], 4.0)]):
+            d = B.CODE_DEFS[name]
+            code = B.Code(d.m, d.prim, d.t)
+            llr_h, cw, d_o_h = gen_point(name, F, ebn0, seed=8000 + ci)
+            truth = pack(cw)
+            llr, d_o = torch.from_numpy(llr_h).to(dev), torch.from_numpy(d_o_h).to(dev)
+            for beta in betas:
+                pcm = B.Pcm.build(code, beta=beta, seed=1)
+                dec = B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8)
+                w, it, fl, sec = timed_decode(dec, llr, d_o, torch, reps=1)
+                rows.append({"code": name, "beta": beta, "rows": pcm.M, "edges": pcm.E, "four_cycles": pcm.c4,
+                             "ebn0": ebn0, "fer": float((w != truth[:, :w.shape[1]]).any(1).mean()),
+                             "avg_iters": float(it.mean()), "frames_per_s": F / sec,
+                             "specialised_kernel": dec.specialized})
+        out.update({"workload": "beta", "config": {"workload": "H_o redundancy sweep, 9 branches, restart mode, "
+                                                              "alpha 0.75, I_m 8, %d frames per point" % F}})
     else:
         points = [2.0, 3.0, 4.0]
         for ci, (name, rows_h) in enumerate([("bch63_45", 33), ("bch63_36", 122)]):
@@ -561,7 +586,7 @@ def main():
         sys.exit(2)
     if args.workload == "serve":
         return run_serve(args)
-    if args.workload in ("alpha", "ablation"):
+    if args.workload in ("alpha", "ablation", "beta"):
         return run_experiment(args)
 
     import torch
