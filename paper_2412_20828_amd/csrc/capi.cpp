@@ -135,6 +135,9 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
     s.llr = llr;
     s.ld = ld;
     s.order = w.order;
+    s.bcur = w.cursor;
+    s.bend = w.end;
+    s.n_buckets = d->prm.n_branches > 1 ? dp : 1;
     s.ranges = w.ranges;
     s.n_ranges = w.n_ranges;
     s.range_counter = w.range_counter;
@@ -148,10 +151,13 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
                      : nullptr;
     s.max_iter = d->prm.max_iter;
     s.alpha = d->prm.alpha;
-    // a batch of F frames has at most ceil(F / range) + dp ranges: no more
-    // persistent waves than that (small batches launch small grids)
+    // no more persistent waves than a batch of F frames can keep busy (small
+    // batches launch small grids): ceil(F / range) + dp ranges, or, for the
+    // kernels that hand out frames one at a time, ceil(F / 64) + dp
+    // workgroups of wave_group waves
     const int64_t grid = (int64_t)d->n_cu * waves_of(d);
-    const int64_t most = (F + range - 1) / range + dp;
+    const int g = d->spec->wave_group;
+    const int64_t most = g > 1 ? g * ((F + 63) / 64 + dp) : (F + range - 1) / range + dp;
     if (most < grid)
         e = d->spec->launch(s, 1, (int)most, stream);
     else

@@ -94,6 +94,7 @@ __global__ void __launch_bounds__(SCAN) bucket_scan(int *__restrict__ blk_hist, 
     if (tid < dp) {
         w.counts[tid] = bucket_total[tid];
         w.cursor[tid] = bucket_start[tid];
+        w.end[tid] = bucket_start[tid] + bucket_total[tid];
     }
     for (int d = 0; d < dp; d++) {
         const int nr = range_start[d + 1] - range_start[d];
@@ -131,7 +132,7 @@ int64_t n_blocks(int64_t F) { return (F + BLK - 1) / BLK; }
 
 size_t bucket_ws_bytes(int64_t F, int dp, int range_frames)
 {
-    const size_t head = align16(sizeof(int) * (2 * (size_t)dp + 2));
+    const size_t head = align16(sizeof(int) * (3 * (size_t)dp + 2));
     const size_t nr = (size_t)(F / range_frames) + dp + 1;
     const size_t hist = align16(sizeof(int) * (size_t)n_blocks(F) * dp);
     return head + nr * sizeof(int4) + hist + align16((size_t)F * sizeof(int));
@@ -144,9 +145,10 @@ BucketWs bucket_ws_carve(void *ws, int64_t F, int dp, int range_frames)
     int *h = reinterpret_cast<int *>(p);
     w.counts = h;
     w.cursor = h + dp;
-    w.n_ranges = h + 2 * dp;
-    w.range_counter = h + 2 * dp + 1;
-    p += align16(sizeof(int) * (2 * (size_t)dp + 2));
+    w.end = h + 2 * dp;
+    w.n_ranges = h + 3 * dp;
+    w.range_counter = h + 3 * dp + 1;
+    p += align16(sizeof(int) * (3 * (size_t)dp + 2));
     w.ranges = reinterpret_cast<int4 *>(p);
     p += ((size_t)(F / range_frames) + dp + 1) * sizeof(int4);
     w.blk_hist = reinterpret_cast<int *>(p);

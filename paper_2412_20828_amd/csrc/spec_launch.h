@@ -14,6 +14,9 @@ struct SpecLaunch {
     const int4 *ranges;    // {start, end, d_o, 0} slices of order
     const int *n_ranges;
     int *range_counter;    // next range to hand out (zeroed by the prepass)
+    int *bcur;             // per bucket: next slot of order to hand out (atomic)
+    const int *bend;       // per bucket: end of its slice of order
+    int n_buckets;
     uint64_t *bits;        // [F][bits_ld] (bits_ld >= W64)
     int64_t bits_ld;
     uint8_t *iters;        // [F]
@@ -26,10 +29,13 @@ struct SpecLaunch {
 
 // Bucketing prepass: groups frames by random offset d_o (reduced modulo d_p;
 // all in bucket 0 for one branch) and cuts every bucket into ranges of at
-// most range_frames frames.
+// most range_frames frames.  Bucket b is order[cursor[b], end[b]) once the
+// prepass is done; kernels that hand out frames one at a time advance
+// cursor[b] atomically.
 struct BucketWs {
     int *counts;
     int *cursor;
+    int *end;
     int *n_ranges;
     int *range_counter;
     int4 *ranges;

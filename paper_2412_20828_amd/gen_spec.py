@@ -17,14 +17,14 @@ import numpy as np
 # (code name, target rows of H_o, n_branches, mode, precision (0 FP32, 1 FIX8),
 #  waves per CU of the persistent grid[, variant: 1 = packed 16-bit fixed point])
 SPECS = [
-    ("bch63_45", 33, 9, 1, 0, 8),
-    ("bch63_36", 122, 9, 1, 0, 8),
-    ("bch63_36", 32, 9, 1, 0, 8),
+    ("bch63_45", 33, 9, 1, 0, 12),
+    ("bch63_36", 122, 9, 1, 0, 12),
+    ("bch63_36", 32, 9, 1, 0, 12),
     ("bch127_99", 33, 9, 1, 0, 4),
     ("bch127_64", 72, 9, 1, 0, 4),
     ("bch127_78", 57, 9, 1, 0, 4),
-    ("bch63_45", 33, 9, 1, 1, 8),
-    ("bch63_36", 122, 9, 1, 1, 8),
+    ("bch63_45", 33, 9, 1, 1, 12),
+    ("bch63_36", 122, 9, 1, 1, 12),
     ("bch127_99", 33, 9, 1, 1, 4),
     ("bch127_64", 72, 9, 1, 1, 4),
     # packed 16-bit fixed point, two frames per lane (opt-in variant)
@@ -282,6 +282,9 @@ def generate(stage1_lib: str, out_dir: str):
         body_path = os.path.join(out_dir, ns + "_body.inc")
         regacc = 1 if N <= 64 and B > 1 else 0
         pk16 = 1 if prec and regacc and variant else 0
+        # nine branches of a short code: three waves (one per automorphism
+        # type) share each 64 frames
+        group = 1 if regacc and B == 9 and not pk16 else 0
         if variant and not pk16:
             raise ValueError("the packed variant needs N <= 64, fixed point and 3 or 9 branches")
         with open(body_path, "w") as fh:
@@ -299,12 +302,13 @@ def generate(stage1_lib: str, out_dir: str):
                      "#define SPEC_Y_GLOBAL %d\n#define SPEC_FIX8 %d\n#define SPEC_REGACC %d\n"
                      % (N, B, ns, waves, yg, prec, regacc))
             fh.write('#define SPEC_BODY "%s"\n' % os.path.basename(body_path))
-            fh.write('#include "%s"\n' % ("nms_spec_pk16.inc" if pk16 else "nms_spec_fp32.inc"))
+            fh.write('#include "%s"\n' % ("nms_spec_pk16.inc" if pk16 else
+                                           "nms_spec_group.inc" if group else "nms_spec_fp32.inc"))
         srcs.append(src_path)
         decls.append("namespace %s { hipError_t launch(const SpecLaunch &, int, int, hipStream_t); }" % ns)
-        entries.append("    {0x%016xull, %d, %d, %d, %d, %d, %d, %d, %d, %d, \"%s\", &%s::launch}," %
+        entries.append("    {0x%016xull, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, \"%s\", &%s::launch}," %
                        (fingerprint(H), N, M, B, mode, prec, variant, waves, 1 if N > 64 else 0,
-                        128 if pk16 else 64, ns, ns))
+                        128 if pk16 else 64, 3 if group else 1, ns, ns))
     table = "\n".join(decls) + "\nstatic const SpecKernel kSpecKernels[] = {\n" + "\n".join(entries) + \
-        "\n    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n"
+        "\n    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n"
     return srcs, table
