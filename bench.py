@@ -61,11 +61,12 @@ WORKLOADS = {
 FIX_SCALE = 4.0
 
 # HBM traffic of the specialised decode kernels, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs at 200,000 frames per launch, each scaled by what the same
+# WRITE_SIZE runs at 1,000,000 frames per launch, each scaled by what the same
 # counter reads for a plain 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE
 # x 1.0).  It holds only for the kernel sources the counters were taken on
-# (hash of the kernel template, its launch header and the row-function
-# generator); any other build reports traffic null.
+# (hash of the grouped kernel template and its rotation helpers, the launch
+# header and the row-function generator); any other build reports traffic
+# null.
 TRAFFIC_SRC_HASH = "3328c51123600d2f"
 TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written) bytes per frame
     "spec_bch63_36_m122_b9": (382.07, 492.75),
@@ -77,7 +78,7 @@ def kernel_src_hash():
     import hashlib
     pkg = os.path.join(ROOT, "paper_2412_20828_amd")
     outer = hashlib.sha256()
-    for f in ("csrc/nms_spec_fp32.inc", "csrc/spec_launch.h", "gen_spec.py"):
+    for f in ("csrc/nms_spec_group.inc", "csrc/nms_spec_rot.inc", "csrc/spec_launch.h", "gen_spec.py"):
         with open(os.path.join(pkg, f), "rb") as fh:
             outer.update(hashlib.sha256(fh.read()).digest())
     return outer.hexdigest()[:16]
