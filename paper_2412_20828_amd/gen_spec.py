@@ -95,15 +95,28 @@ def fingerprint(H: np.ndarray) -> int:
     return h
 
 
-def _min(a, b):
-    """min(a, b) as med3(a, b, -inf): the same value for non-NaN inputs, and
-    unlike fminf it needs no canonicalised copies of its operands (which
-    would double the live registers of the magnitude array)."""
-    return "__builtin_amdgcn_fmed3f(%s, %s, -__builtin_inff())" % (a, b)
+# The min1/min2 chain runs on the bit patterns of the magnitudes: non-negative
+# floats order as their bit patterns, so integer min and med3 give the same
+# values as the float ones, and on gfx950 they issue beside the float med3 of
+# the c2v selection instead of competing with it.  The min/max tree below is
+# matched to a single v_med3_u32.
+_MED3U = """__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c)
+{
+    return min(max(a, b), max(min(a, b), c));
+}
+"""
 
 
-def _max(a, b):
-    return "__builtin_amdgcn_fmed3f(%s, %s, __builtin_inff())" % (a, b)
+def _forward(cols):
+    """Lines of a row's min1 <= min2 chain over A[cols] in integer form,
+    ending with float m1, m2."""
+    c0, c1 = cols[0], cols[1]
+    out = ["        uint32_t u1 = min(__float_as_uint(A[%d]), __float_as_uint(A[%d])), "
+           "u2 = max(__float_as_uint(A[%d]), __float_as_uint(A[%d]));" % (c0, c1, c0, c1)]
+    for c in cols[2:]:
+        out.append("        u2 = med3u(u1, u2, __float_as_uint(A[%d])); u1 = min(u1, __float_as_uint(A[%d]));" % (c, c))
+    out.append("        const float m1 = __uint_as_float(u1), m2 = __uint_as_float(u2);")
+    return out
 
 
 def body_source(H: np.ndarray, accumulate: bool = False) -> str:
@@ -111,7 +124,7 @@ def body_source(H: np.ndarray, accumulate: bool = False) -> str:
     T (T holds a running sum over branches) instead of overwriting T."""
     M, N = H.shape
     W32 = (N + 31) // 32
-    out = ["__device__ __forceinline__ void body(const float *__restrict__ A, "
+    out = [_MED3U, "__device__ __forceinline__ void body(const float *__restrict__ A, "
            "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
     touched = [False] * N
     for j in range(M):
@@ -123,10 +136,7 @@ def body_source(H: np.ndarray, accumulate: bool = False) -> str:
         out.append("    { // row %d" % j)
         out.append("        const uint32_t cnt = %s;" % cnt)
         out.append("        const float sg = __uint_as_float(0x3f800000u | (cnt << 31));")
-        c0, c1 = cols[0], cols[1]
-        out.append("        float m1 = %s, m2 = %s;" % (_min("A[%d]" % c0, "A[%d]" % c1), _max("A[%d]" % c0, "A[%d]" % c1)))
-        for c in cols[2:]:
-            out.append("        m2 = __builtin_amdgcn_fmed3f(m1, m2, A[%d]); m1 = %s;" % (c, _min("m1", "A[%d]" % c)))
+        out += _forward(cols)
         out.append("        const float P = m1 + m2;")
         for c in cols:
             mag = "__builtin_amdgcn_fmed3f(m1, m2, P - A[%d])" % c
@@ -153,7 +163,7 @@ def body_source_fix8(H: np.ndarray, accumulate: bool = False) -> str:
     integers, so every step is exact."""
     M, N = H.shape
     W32 = (N + 31) // 32
-    out = ["__device__ __forceinline__ void body(const float *__restrict__ A, "
+    out = [_MED3U, "__device__ __forceinline__ void body(const float *__restrict__ A, "
            "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
     touched = [False] * N
     for j in range(M):
@@ -165,10 +175,7 @@ def body_source_fix8(H: np.ndarray, accumulate: bool = False) -> str:
         out.append("    { // row %d" % j)
         out.append("        const uint32_t cnt = %s;" % cnt)
         out.append("        const float sg = __uint_as_float(0x3f800000u | (cnt << 31));")
-        c0, c1 = cols[0], cols[1]
-        out.append("        float m1 = %s, m2 = %s;" % (_min("A[%d]" % c0, "A[%d]" % c1), _max("A[%d]" % c0, "A[%d]" % c1)))
-        for c in cols[2:]:
-            out.append("        m2 = __builtin_amdgcn_fmed3f(m1, m2, A[%d]); m1 = %s;" % (c, _min("m1", "A[%d]" % c)))
+        out += _forward(cols)
         out.append("        const float q1 = floorf(__builtin_fmaf(m1, 0.75f, 0.5f)), "
                    "q2 = floorf(__builtin_fmaf(m2, 0.75f, 0.5f));")
         out.append("        const float K = __builtin_fmaf(m1, 128.0f, q2);")

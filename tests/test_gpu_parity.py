@@ -207,6 +207,50 @@ def test_results_independent_of_batch_composition(B):
     assert torch.equal(one[0][0], full[0][100]) and torch.equal(one[1][0], full[1][100])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_skewed_offsets_every_frame_decoded(B, precision):
+    """Offsets concentrated in two buckets (d_o mod d_p), and a batch whose
+    frames all share one offset: the workgroups of the grouped kernel crowd
+    onto few buckets' cursors and move between buckets as they run dry.
+    Every frame gets its outputs (iterations pre-filled with 0xff), and a
+    sample equals the oracle (FP32: the parity bar; int8: bit-exact)."""
+    name, rows, F = "bch63_45", 33, 300_000
+    c, p = lib_objects(B, name, rows)
+    oc = oracle_code(name)
+    H = oracle_hopt(name, rows)
+    dec = B.Decoder(c, p, n_branches=9, max_iter=8, precision=precision)
+    assert dec.specialized
+    fr = synth.frames(name, F, 2.5, seed=31)
+    rng = np.random.default_rng(5)
+    cases = [np.where(rng.random(F) < 0.85, 5, 17).astype(np.uint8), np.full(F, 19, np.uint8)]
+    for d_o_h in cases:
+        llr = torch.from_numpy(fr.llr).cuda()
+        if precision:
+            q = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
+            B.quantize_llr(llr, c.N, 4.0, q)
+            llr = q
+        bits = torch.empty((F, 1), dtype=torch.int64, device="cuda")
+        iters = torch.full((F,), 255, dtype=torch.uint8, device="cuda")
+        flg = torch.full((F,), 255, dtype=torch.uint8, device="cuda")
+        ws = torch.empty(dec.workspace_size(F), dtype=torch.uint8, device="cuda")
+        dec.decode_into(llr, torch.from_numpy(d_o_h).cuda(), bits, iters, flg, workspace=ws)
+        torch.cuda.synchronize()
+        it_h, fl_h = iters.cpu().numpy(), flg.cpu().numpy()
+        assert ((it_h >= 1) & (it_h <= 8)).all() and (fl_h <= 1).all()
+        pick = np.sort(rng.choice(F, 3000, replace=False))
+        words = B.unpack_bits(bits.cpu().numpy().view(np.uint64)[pick], c.N)
+        src = llr.cpu().numpy()[pick]
+        if precision:
+            oc_, oit, ocv = oracle.decode_batch(H, oc.Hstd, src, d_o_h[pick], 9, 0.75, 8, oracle.R1,
+                                                kind=oracle.KIND_FIXED, threads=8)
+            assert np.array_equal(words, oc_) and np.array_equal(it_h[pick], oit)
+            assert np.array_equal(fl_h[pick].astype(bool), ocv)
+        else:
+            oc_, oit, ocv, otr = oracle.decode_batch(H, oc.Hstd, src, d_o_h[pick], 9, 0.75, 8, oracle.R1,
+                                                     threads=8, trace=True)
+            compare_with_oracle(words, it_h[pick], fl_h[pick], None, oc_, oit, ocv, otr)
+
+
 # ------------------------------------------------------------ fixed point
 def run_fix8_pair(B, name, rows, F, ebn0, seed, scale=4.0, flags=0):
     c, p = lib_objects(B, name, rows)
