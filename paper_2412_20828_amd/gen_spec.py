@@ -287,11 +287,11 @@ def generate(stage1_lib: str, out_dir: str):
         M, N = H.shape
         ns = "spec_%s_m%d_b%d%s%s" % (name, M, B, "_fix8" if prec else "", "_pk16" if variant else "")
         body_path = os.path.join(out_dir, ns + "_body.inc")
-        regacc = 1 if N <= 64 and B > 1 else 0
-        pk16 = 1 if prec and regacc and variant else 0
+        regacc = 1 if B > 1 else 0
+        pk16 = 1 if prec and regacc and N <= 64 and variant else 0
         # nine branches of a short code: three waves (one per automorphism
         # type) share each 64 frames
-        group = 1 if regacc and B == 9 and not pk16 else 0
+        group = 1 if regacc and N <= 64 and B == 9 and not pk16 else 0
         if variant and not pk16:
             raise ValueError("the packed variant needs N <= 64, fixed point and 3 or 9 branches")
         with open(body_path, "w") as fh:
@@ -304,7 +304,7 @@ def generate(stage1_lib: str, out_dir: str):
         src_path = os.path.join(out_dir, ns + ".hip")
         with open(src_path, "w") as fh:
             fh.write('#include "spec_launch.h"\n')
-            yg = 1 if N > 64 else 0
+            yg = 1 if N > 64 and not regacc else 0
             fh.write("#define SPEC_N %d\n#define SPEC_B %d\n#define SPEC_NS %s\n#define SPEC_WAVES %d\n"
                      "#define SPEC_Y_GLOBAL %d\n#define SPEC_FIX8 %d\n#define SPEC_REGACC %d\n"
                      % (N, B, ns, waves, yg, prec, regacc))
@@ -314,7 +314,7 @@ def generate(stage1_lib: str, out_dir: str):
         srcs.append(src_path)
         decls.append("namespace %s { hipError_t launch(const SpecLaunch &, int, int, hipStream_t); }" % ns)
         entries.append("    {0x%016xull, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, \"%s\", &%s::launch}," %
-                       (fingerprint(H), N, M, B, mode, prec, variant, waves, 1 if N > 64 else 0,
+                       (fingerprint(H), N, M, B, mode, prec, variant, waves, 1 if N > 64 and not regacc else 0,
                         128 if pk16 else 64, 3 if group else 1, ns, ns))
     table = "\n".join(decls) + "\nstatic const SpecKernel kSpecKernels[] = {\n" + "\n".join(entries) + \
         "\n    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n"
