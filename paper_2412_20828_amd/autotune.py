@@ -1,11 +1,13 @@
 """Autotuner of the specialised decoders' launch shape.
 
-Knobs: frames per range handed to a persistent wave (the unit of work a wave
-takes from the range counter) and waves per CU of the persistent grid.  The
-tuner times every candidate on a synthetic batch of the decoder's own code at
-a given Eb/N0 and keeps the fastest; results are cached in tuning.json beside
-this file, keyed by (code, rows of H_o, precision, branches, GPU name), and
-applied by apply_cached().
+Knobs: waves per CU of the persistent grid (frames per workgroup follow from
+it: 64 per one-wave workgroup, 64 per three-wave group of the nine-branch N = 63
+kernels) and, with ranges=True, frames per range for the packed 16-bit kernels,
+the only ones that still take ranges rather than single frames from per-bucket
+cursors.  The tuner times every candidate on a synthetic batch of the
+decoder's own code at a given Eb/N0 and keeps the fastest; results are cached
+in tuning.json beside this file, keyed by (code, rows of H_o, precision,
+branches, GPU name), and applied by apply_cached().
 """
 from __future__ import annotations
 
@@ -16,7 +18,7 @@ import time
 _HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(_HERE, "tuning.json")
 RANGE_FRAMES = [128, 256, 512, 1024, 2048]
-WAVES = [0, 2, 3, 4, 5, 6, 8, 10, 12]
+WAVES = [0, 2, 3, 4, 6, 8, 9, 12]
 
 
 def key(code_name: str, rows: int, precision: int, n_branches: int, gpu: str) -> str:
@@ -45,7 +47,7 @@ def apply_cached(decoder, code_name: str, rows: int) -> bool:
 
 
 def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 400_000, reps: int = 3,
-         seed: int = 99, write: bool = True):
+         seed: int = 99, write: bool = True, ranges: bool = False):
     """Time every candidate and return the best (also cached when write)."""
     import numpy as np
     import torch
@@ -64,7 +66,7 @@ def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 40
     it = torch.empty(F, dtype=torch.uint8, device="cuda")
     fl = torch.empty(F, dtype=torch.uint8, device="cuda")
     results = []
-    for rf in RANGE_FRAMES:
+    for rf in (RANGE_FRAMES if ranges else [256]):
         for wv in WAVES:
             decoder.set_tuning(rf, wv)
             ws = torch.empty(max(1, decoder.workspace_size(F)), dtype=torch.uint8, device="cuda")

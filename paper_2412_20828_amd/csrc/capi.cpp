@@ -153,11 +153,12 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
     s.alpha = d->prm.alpha;
     // no more persistent waves than a batch of F frames can keep busy (small
     // batches launch small grids): ceil(F / range) + dp ranges, or, for the
-    // kernels that hand out frames one at a time, ceil(F / 64) + dp
+    // kernels that hand out frames from per-bucket cursors, ceil(F / 64) + dp
     // workgroups of wave_group waves
     const int64_t grid = (int64_t)d->n_cu * waves_of(d);
     const int g = d->spec->wave_group;
-    const int64_t most = g > 1 ? g * ((F + 63) / 64 + dp) : (F + range - 1) / range + dp;
+    const int64_t fw = d->spec->frames_per_wave;
+    const int64_t most = d->spec->cursor ? g * ((F + fw - 1) / fw + dp) : (F + range - 1) / range + dp;
     if (most < grid)
         e = d->spec->launch(s, 1, (int)most, stream);
     else
