@@ -46,7 +46,15 @@ def apply_cached(decoder, code_name: str, rows: int) -> bool:
     return True
 
 
-def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 400_000, reps: int = 3,
+def default_frames(N: int) -> int:
+    """Batch size of the tuning runs: the per-launch frames of the sweep (N = 63)
+    and of the 127-bit workloads.  The best grid depends on it: a smaller batch
+    favours fewer resident frames, whose drain at the end of the launch is
+    shorter."""
+    return 1_000_000 if N <= 64 else 4_000_000
+
+
+def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 0, reps: int = 3,
          seed: int = 99, write: bool = True, ranges: bool = False):
     """Time every candidate and return the best (also cached when write)."""
     import numpy as np
@@ -54,6 +62,7 @@ def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 40
 
     import synth
     from . import binding as B
+    frames = frames or default_frames(decoder.N)
     fr = synth.frames(code_name, frames, ebn0, seed=seed)
     llr = torch.from_numpy(fr.llr).cuda()
     if decoder.precision == B.FIX8:
@@ -65,6 +74,13 @@ def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 40
     bits = torch.empty((F, decoder.W64), dtype=torch.int64, device="cuda")
     it = torch.empty(F, dtype=torch.uint8, device="cuda")
     fl = torch.empty(F, dtype=torch.uint8, device="cuda")
+    # warm the clocks and caches first, so that the first candidate is not
+    # timed on a cold GPU
+    decoder.set_tuning(0, 0)
+    ws = torch.empty(max(1, decoder.workspace_size(F)), dtype=torch.uint8, device="cuda")
+    for _ in range(2 * reps):
+        decoder.decode_into(llr, d_o, bits, it, fl, workspace=ws)
+    torch.cuda.synchronize()
     results = []
     for rf in (RANGE_FRAMES if ranges else [256]):
         for wv in WAVES:
@@ -81,7 +97,7 @@ def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 40
     results.sort()
     dt, rf, wv = results[0]
     decoder.set_tuning(rf, wv)
-    best = {"range_frames": rf, "waves_per_cu": wv, "frames_per_s": F / dt, "ebn0": ebn0,
+    best = {"range_frames": rf, "waves_per_cu": wv, "frames_per_s": F / dt, "ebn0": ebn0, "frames": F,
             "default_frames_per_s": F / next(d for d, r, w in results if r == 256 and w == 0)}
     if write:
         cache = load()
@@ -98,7 +114,7 @@ def main():
     ap.add_argument("--codes", default="bch127_64:72,bch127_99:33,bch63_36:122,bch63_45:33")
     ap.add_argument("--precisions", default="fp32,fix8")
     ap.add_argument("--ebn0", type=float, default=3.0)
-    ap.add_argument("--frames", type=int, default=400_000)
+    ap.add_argument("--frames", type=int, default=0, help="frames per timed launch (0: 10^6 for N = 63, 4 10^6 for N = 127)")
     ap.add_argument("--out", default=CACHE, help="JSON cache to update")
     args = ap.parse_args()
     CACHE = args.out
