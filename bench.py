@@ -318,6 +318,7 @@ def run_serve(args):
     done, wall = serving.run_trace(eng, fresh(), [0.0] * len(tr))
     sat = serving.summarize(done, wall)
     sat["launches"] = eng.launches
+    sat["hw_queues"] = os.environ.get("GPU_MAX_HW_QUEUES")
     truth = {k: f.codewords for k, f in enumerate(frs)}
     fer_h = np.mean(np.concatenate([(r.bits != pack(truth[r.rid])).any(1) for r in done]))
     fer_n = np.mean(np.concatenate([((r.flags & serving.FLAG_OSD) != 0) | (r.bits != pack(truth[r.rid])).any(1)
@@ -586,6 +587,11 @@ def main():
         print("bench.py: this build measures one GPU; --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload == "serve":
+        # one hardware queue per stream of the engine (serving.hw_queues),
+        # raised before anything starts HIP
+        need = min(32, args.slots * (len(SERVE_CODES) + 1) + 1)
+        if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < need:
+            os.environ["GPU_MAX_HW_QUEUES"] = str(need)
         return run_serve(args)
     if args.workload in ("alpha", "ablation", "beta"):
         return run_experiment(args)

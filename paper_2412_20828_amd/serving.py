@@ -6,9 +6,12 @@ and branch tables) resident on the device and owns a fixed set of slots,
 each a preallocated batch of pinned host staging, device buffers and a HIP
 stream.  Whenever a slot is free, the pending requests are packed into it in
 arrival order up to the slot's frame capacity (admission by memory: a slot
-never holds more than it was sized for) and the whole batch is decoded in one
-mixed-code call; slots run on their own streams, so the batch of a newly
-admitted request overlaps on the device with the batches already in flight.
+never holds more than it was sized for).  Inside the slot each code's frames
+are contiguous, and every code present is decoded by its own call on a stream
+of the slot's own, so the codes of a batch run side by side on the device
+(a batch takes as long as its slowest code, not the sum of its codes).  Slots
+run on their own streams too, so the batch of a newly admitted request
+overlaps on the device with the batches already in flight.
 Frames whose syndrome is still nonzero go to order-p OSD on their channel
 LLRs (the hybrid of Section II-B and the complexity account C_t = C_1 +
 F_1 C_2 of Section IV), either on the device, enqueued on the slot's stream
@@ -20,6 +23,12 @@ of its frames have a decision.
 
 Every frame decodes exactly as it would alone: the kernel's arithmetic for a
 frame depends only on that frame's LLRs and offset, and OSD is deterministic.
+
+A slot uses 1 + (number of codes) streams.  HIP maps a process's streams onto
+GPU_MAX_HW_QUEUES hardware queues (4 by default), and streams that share a
+queue run in submission order, so with too few queues one slot's copies wait
+behind another slot's kernels.  A serving process should set the variable to
+at least hw_queues(n_slots, n_codes) before HIP initialises.
 """
 from __future__ import annotations
 
@@ -34,6 +43,12 @@ from . import binding as B
 
 FLAG_CONVERGED = 1
 FLAG_OSD = 2
+
+
+def hw_queues(n_slots: int, n_codes: int) -> int:
+    """Hardware queues that give every stream of the engine its own (plus one
+    for the default stream), capped at 32."""
+    return min(32, n_slots * (n_codes + 1) + 1)
 
 
 @dataclass
@@ -58,13 +73,14 @@ class Request:
 
 @dataclass
 class _Slot:
-    stream: object
-    event: object
+    stream: object          # copies in and out
+    event: object           # results back on the host
+    copied: object          # inputs on the device
+    code_streams: list      # per code: its decode (and device OSD)
+    code_done: list         # per code: event after its last kernel
     h_llr: object
-    h_ci: object
     h_do: object
     d_llr: object
-    d_ci: object
     d_do: object
     d_bits: object
     d_iters: object
@@ -72,7 +88,7 @@ class _Slot:
     h_bits: object
     h_iters: object
     h_flags: object
-    ws: object
+    wss: list               # per code workspace
     members: list = field(default_factory=list)   # (request, offset)
     busy: bool = False
 
@@ -108,10 +124,12 @@ class Engine:
             self.decs.append(dec)
         if precision != B.FP32:
             raise B.BchError("the service takes FP32 LLRs (quantise per code for int8 decoders)")
-        self.mix = B.MixedDecoder(self.decs)
-        self._mixes = {}
+        # one-code calls of the mixed entry point: they take the slot's row
+        # stride for the decisions, and an all-zero code index
+        self.mixes1 = [B.MixedDecoder([d]) for d in self.decs]
         self.cap = slot_frames
-        self.ld = self.mix.ld
+        self.ld = B.MixedDecoder(self.decs).ld
+        self.d_zero = torch.zeros(slot_frames, dtype=torch.uint8, device=self.dev)
         if osd_on not in ("device", "host"):
             raise B.BchError("osd_on must be 'device' or 'host'")
         self.osd_order = osd_order
@@ -120,24 +138,25 @@ class Engine:
         self.pending = collections.deque()
         self.osd_pool = ThreadPoolExecutor(1) if osd_order is not None and osd_on == "host" else None
         self.osd_jobs = []
-        ws_bytes = max(1, self.mix.workspace_size(slot_frames))
+        ws_bytes = [max(1, m.workspace_size(slot_frames)) for m in self.mixes1]
         self.slots = []
         for _ in range(n_slots):
             pin = dict(pin_memory=True)
             cap, ld = slot_frames, self.ld
             self.slots.append(_Slot(
-                stream=torch.cuda.Stream(device=self.dev), event=torch.cuda.Event(),
+                stream=torch.cuda.Stream(device=self.dev), event=torch.cuda.Event(), copied=torch.cuda.Event(),
+                code_streams=[torch.cuda.Stream(device=self.dev) for _ in self.decs],
+                code_done=[torch.cuda.Event() for _ in self.decs],
                 h_llr=torch.empty((cap, ld), dtype=torch.float32, **pin),
-                h_ci=torch.empty(cap, dtype=torch.uint8, **pin), h_do=torch.empty(cap, dtype=torch.uint8, **pin),
+                h_do=torch.empty(cap, dtype=torch.uint8, **pin),
                 d_llr=torch.empty((cap, ld), dtype=torch.float32, device=self.dev),
-                d_ci=torch.empty(cap, dtype=torch.uint8, device=self.dev),
                 d_do=torch.empty(cap, dtype=torch.uint8, device=self.dev),
                 d_bits=torch.zeros((cap, 2), dtype=torch.int64, device=self.dev),
                 d_iters=torch.empty(cap, dtype=torch.uint8, device=self.dev),
                 d_flags=torch.empty(cap, dtype=torch.uint8, device=self.dev),
                 h_bits=torch.empty((cap, 2), dtype=torch.int64, **pin),
                 h_iters=torch.empty(cap, dtype=torch.uint8, **pin), h_flags=torch.empty(cap, dtype=torch.uint8, **pin),
-                ws=torch.empty(ws_bytes, dtype=torch.uint8, device=self.dev)))
+                wss=[torch.empty(b, dtype=torch.uint8, device=self.dev) for b in ws_bytes]))
         self.launches = 0
         self.frames_launched = 0
 
@@ -192,59 +211,55 @@ class Engine:
 
     def _launch(self, s: _Slot):
         torch = self.torch
-        n = 0
-        s.members = []
-        hl, hc, hd = s.h_llr.numpy(), s.h_ci.numpy(), s.h_do.numpy()
-        now = time.perf_counter()
-        present = sorted({r.code for r in self._admissible()})
-        local = {c: k for k, c in enumerate(present)}
+        take, n = [], 0
         while self.pending and n + self.pending[0].frames <= self.cap:
             r = self.pending.popleft()
-            F, w = r.frames, min(r.llr.shape[1], self.ld)
-            hl[n:n + F, :w] = r.llr[:, :w]
-            hc[n:n + F] = local[r.code]
-            hd[n:n + F] = r.d_o
-            r.t_admit = now
-            s.members.append((r, n))
-            n += F
-        if n == 0:
+            take.append(r)
+            n += r.frames
+        if not take:
             return
+        # each code's frames contiguous, requests in arrival order inside it
+        counts = [0] * len(self.decs)
+        for r in take:
+            counts[r.code] += r.frames
+        start = [0] * len(self.decs)
+        for c in range(1, len(self.decs)):
+            start[c] = start[c - 1] + counts[c - 1]
+        pos = list(start)
+        hl, hd = s.h_llr.numpy(), s.h_do.numpy()
+        now = time.perf_counter()
+        s.members = []
+        for r in take:
+            off, F, w = pos[r.code], r.frames, min(r.llr.shape[1], self.ld)
+            hl[off:off + F, :w] = r.llr[:, :w]
+            hd[off:off + F] = r.d_o
+            r.t_admit = now
+            s.members.append((r, off))
+            pos[r.code] += F
         with torch.cuda.stream(s.stream):
             s.d_llr[:n].copy_(s.h_llr[:n], non_blocking=True)
-            s.d_ci[:n].copy_(s.h_ci[:n], non_blocking=True)
             s.d_do[:n].copy_(s.h_do[:n], non_blocking=True)
-            mix = self._mix(present)
-            mix.decode_into(s.d_ci[:n], s.d_llr[:n], s.d_do[:n], s.d_bits[:n], s.d_iters[:n], s.d_flags[:n], s.ws,
-                            stream=s.stream)
+        s.copied.record(s.stream)
+        for c, cnt in enumerate(counts):
+            if not cnt:
+                continue
+            st, seg, m = s.code_streams[c], slice(start[c], start[c] + cnt), self.mixes1[c]
+            st.wait_event(s.copied)
+            m.decode_into(self.d_zero[:cnt], s.d_llr[seg], s.d_do[seg], s.d_bits[seg], s.d_iters[seg],
+                          s.d_flags[seg], s.wss[c], stream=st)
             if self.osd_order is not None and self.osd_on == "device":
-                mix.osd_into(s.d_ci[:n], s.d_llr[:n], self.osd_order, s.d_bits[:n], skip=s.d_flags[:n],
-                             stream=s.stream)
+                m.osd_into(self.d_zero[:cnt], s.d_llr[seg], self.osd_order, s.d_bits[seg], skip=s.d_flags[seg],
+                           stream=st)
+            s.code_done[c].record(st)
+            s.stream.wait_event(s.code_done[c])
+        with torch.cuda.stream(s.stream):
             s.h_bits[:n].copy_(s.d_bits[:n], non_blocking=True)
             s.h_iters[:n].copy_(s.d_iters[:n], non_blocking=True)
             s.h_flags[:n].copy_(s.d_flags[:n], non_blocking=True)
-            s.event.record(s.stream)
+        s.event.record(s.stream)
         s.busy = True
         self.launches += 1
         self.frames_launched += n
-
-    def _admissible(self):
-        """The pending requests the next launch takes (arrival order, up to
-        the slot capacity)."""
-        n = 0
-        for r in self.pending:
-            if n + r.frames > self.cap:
-                break
-            n += r.frames
-            yield r
-
-    def _mix(self, present):
-        """Mixed decoder over the codes present in a batch (kernels are
-        enqueued only for those codes)."""
-        key = tuple(present)
-        m = self._mixes.get(key)
-        if m is None:
-            m = self._mixes[key] = B.MixedDecoder([self.decs[c] for c in present])
-        return m
 
     def _finish_slot(self, s: _Slot):
         done = []
