@@ -161,7 +161,8 @@ size_t bch_decode_workspace_size(bch_decoder dec, int64_t F);
  * int32 for FIX8) per-iteration posteriors y^(t), or NULL (rows past a
  * frame's last iteration are left untouched).  workspace: device, at least
  * bch_decode_workspace_size(dec, F) bytes (may be NULL when that is 0).
- * Enqueued on stream. */
+ * 0 <= F <= BCH_MAX_FRAMES (BCH_EINVAL otherwise).  Enqueued on stream. */
+#define BCH_MAX_FRAMES ((int64_t)1 << 30)
 int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F,
                          const uint8_t *d_o, uint64_t *bits, uint8_t *iters,
                          uint8_t *flags, void *y_trace, void *workspace,
@@ -185,8 +186,8 @@ int bch_decoder_set_tuning(bch_decoder dec, int range_frames, int waves_per_cu);
  * n_codes are left untouched).  Every decoder needs a specialised kernel and
  * all share the precision.  llr: device [F][ld] with ld >= every N; bits:
  * device [F][bits_ld] uint64, bits_ld >= every ceil(N/64); iters, flags: as
- * bch_nms_decode_batch.  One prepass and one persistent kernel per code are
- * enqueued on stream (no host synchronisation, no memset: the call can be
+ * bch_nms_decode_batch; F <= BCH_MAX_FRAMES.  One prepass and one persistent
+ * kernel per code are enqueued on stream (no host synchronisation, no memset: the call can be
  * captured in a HIP graph and replayed).  Per-frame results do not depend on
  * the mix: each frame decodes exactly as alone.
  */

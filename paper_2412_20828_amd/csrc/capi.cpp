@@ -457,7 +457,9 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
 {
     if (!dec)
         return fail(BCH_EINVAL, "decoder is NULL");
-    if (F < 0 || F > (int64_t)1 << 31)
+    // the frame cursors are 32-bit and may run past a bucket's end by a few
+    // grabs of 64; the cap keeps them far from overflow
+    if (F < 0 || F > BCH_MAX_FRAMES)
         return fail(BCH_EINVAL, "F out of range");
     if (F == 0)
         return BCH_OK;
@@ -540,7 +542,9 @@ int bch_mixed_decode_batch(const bch_decoder *decs, int n_codes, const uint8_t *
 {
     if (!decs || n_codes < 1 || n_codes > BCH_MAX_MIX)
         return fail(BCH_EINVAL, "n_codes must be in [1, BCH_MAX_MIX]");
-    if (F < 0 || F > (int64_t)1 << 31)
+    // the frame cursors are 32-bit and may run past a bucket's end by a few
+    // grabs of 64; the cap keeps them far from overflow
+    if (F < 0 || F > BCH_MAX_FRAMES)
         return fail(BCH_EINVAL, "F out of range");
     if (F == 0)
         return BCH_OK;
