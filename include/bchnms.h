@@ -187,9 +187,9 @@ int bch_decoder_set_tuning(bch_decoder dec, int range_frames, int waves_per_cu);
  * all share the precision.  llr: device [F][ld] with ld >= every N; bits:
  * device [F][bits_ld] uint64, bits_ld >= every ceil(N/64); iters, flags: as
  * bch_nms_decode_batch; F <= BCH_MAX_FRAMES.  One prepass and one persistent
- * kernel per code are enqueued on stream (no host synchronisation, no memset: the call can be
- * captured in a HIP graph and replayed).  Per-frame results do not depend on
- * the mix: each frame decodes exactly as alone.
+ * kernel per code are enqueued on stream (no host synchronisation, no memset:
+ * the call can be captured in a HIP graph and replayed).  Per-frame results do
+ * not depend on the mix: each frame decodes exactly as alone.
  */
 #define BCH_MAX_MIX 8
 size_t bch_mixed_workspace_size(const bch_decoder *decs, int n_codes, int64_t F);
