@@ -168,17 +168,13 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
                          uint8_t *flags, void *y_trace, void *workspace,
                          size_t ws_bytes, hipStream_t stream);
 
-/* Tuning of a specialised decoder (autotuner hook).  waves_per_cu: waves per
- * CU of the persistent grid (0: the kernel's default; the nine-branch N = 63
- * kernels run workgroups of three waves, so waves_per_cu / 3 of them per CU).
- * A decode of F frames never launches more than its frames can occupy.
- * range_frames (0: 256): frames per range handed to a persistent wave, for
- * the packed 16-bit kernels, the only ones that take ranges (the others take
- * single frames from per-offset-bucket cursors); a decode of F frames uses at
- * most F / (persistent waves), rounded down to a multiple of the wave's frames
- * and at least that.  Changes bch_decode_workspace_size.  No effect on the
- * generic kernel.  Not thread-safe against a concurrent decode. */
-int bch_decoder_set_tuning(bch_decoder dec, int range_frames, int waves_per_cu);
+/* Tuning of a specialised decoder (autotuner hook): waves per CU of the
+ * persistent grid (0: the kernel's default; the nine-branch N = 63 kernels
+ * run workgroups of three waves, so waves_per_cu / 3 of them per CU).  A
+ * decode of F frames never launches more than its frames can occupy.  No
+ * effect on the generic kernel.  Not thread-safe against a concurrent
+ * decode. */
+int bch_decoder_set_tuning(bch_decoder dec, int waves_per_cu);
 
 /* ------------------------------------------------------------------------
  * Mixed-code batch: the frames of up to BCH_MAX_MIX codes interleaved in one

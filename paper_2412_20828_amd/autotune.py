@@ -1,13 +1,12 @@
 """Autotuner of the specialised decoders' launch shape.
 
-Knobs: waves per CU of the persistent grid (frames per workgroup follow from
-it: 64 per one-wave workgroup, 64 per three-wave group of the nine-branch N = 63
-kernels) and, with ranges=True, frames per range for the packed 16-bit kernels,
-the only ones that still take ranges rather than single frames from per-bucket
-cursors.  The tuner times every candidate on a synthetic batch of the
-decoder's own code at a given Eb/N0 and keeps the fastest; results are cached
-in tuning.json beside this file, keyed by (code, rows of H_o, precision,
-branches, GPU name), and applied by apply_cached().
+Knob: waves per CU of the persistent grid (the frames per workgroup are fixed
+by the kernel: 64 per one-wave workgroup and per three-wave group of the
+nine-branch N = 63 kernels, 128 for the packed 16-bit kernels).  The tuner
+times every candidate on a synthetic batch of the decoder's own code at a
+given Eb/N0 and keeps the fastest; results are cached in tuning.json beside
+this file, keyed by (code, rows of H_o, precision, branches, GPU name), and
+applied by apply_cached().
 """
 from __future__ import annotations
 
@@ -17,7 +16,6 @@ import time
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(_HERE, "tuning.json")
-RANGE_FRAMES = [128, 256, 512, 1024, 2048]
 WAVES = [0, 2, 3, 4, 6, 8, 9, 12]
 
 
@@ -42,7 +40,7 @@ def apply_cached(decoder, code_name: str, rows: int) -> bool:
     entry = load().get(key(code_name, rows, decoder.precision, decoder.n_branches, _gpu_name()))
     if not entry or not decoder.specialized:
         return False
-    decoder.set_tuning(entry["range_frames"], entry["waves_per_cu"])
+    decoder.set_tuning(entry["waves_per_cu"])
     return True
 
 
@@ -55,7 +53,7 @@ def default_frames(N: int) -> int:
 
 
 def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 0, reps: int = 3,
-         seed: int = 99, write: bool = True, ranges: bool = False):
+         seed: int = 99, write: bool = True):
     """Time every candidate and return the best (also cached when write)."""
     import numpy as np
     import torch
@@ -76,29 +74,28 @@ def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 0,
     fl = torch.empty(F, dtype=torch.uint8, device="cuda")
     # warm the clocks and caches first, so that the first candidate is not
     # timed on a cold GPU
-    decoder.set_tuning(0, 0)
+    decoder.set_tuning(0)
     ws = torch.empty(max(1, decoder.workspace_size(F)), dtype=torch.uint8, device="cuda")
     for _ in range(2 * reps):
         decoder.decode_into(llr, d_o, bits, it, fl, workspace=ws)
     torch.cuda.synchronize()
     results = []
-    for rf in (RANGE_FRAMES if ranges else [256]):
-        for wv in WAVES:
-            decoder.set_tuning(rf, wv)
-            ws = torch.empty(max(1, decoder.workspace_size(F)), dtype=torch.uint8, device="cuda")
+    for wv in WAVES:
+        decoder.set_tuning(wv)
+        ws = torch.empty(max(1, decoder.workspace_size(F)), dtype=torch.uint8, device="cuda")
+        decoder.decode_into(llr, d_o, bits, it, fl, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
             decoder.decode_into(llr, d_o, bits, it, fl, workspace=ws)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                decoder.decode_into(llr, d_o, bits, it, fl, workspace=ws)
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / reps
-            results.append((dt, rf, wv))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        results.append((dt, wv))
     results.sort()
-    dt, rf, wv = results[0]
-    decoder.set_tuning(rf, wv)
-    best = {"range_frames": rf, "waves_per_cu": wv, "frames_per_s": F / dt, "ebn0": ebn0, "frames": F,
-            "default_frames_per_s": F / next(d for d, r, w in results if r == 256 and w == 0)}
+    dt, wv = results[0]
+    decoder.set_tuning(wv)
+    best = {"waves_per_cu": wv, "frames_per_s": F / dt, "ebn0": ebn0, "frames": F,
+            "default_frames_per_s": F / next(d for d, w in results if w == 0)}
     if write:
         cache = load()
         cache[key(code_name, rows, decoder.precision, decoder.n_branches, _gpu_name())] = best
@@ -131,8 +128,8 @@ def main():
                 print("%s/%d/%s: no specialised kernel, skipped" % (name, rows, prec), flush=True)
                 continue
             best, res = tune(dec, name, rows, ebn0=args.ebn0, frames=args.frames)
-            print("%s/%d/%s: best range %d waves %d: %.1fM frames/s (default %.1fM)" % (
-                name, rows, prec, best["range_frames"], best["waves_per_cu"], best["frames_per_s"] / 1e6,
+            print("%s/%d/%s: best waves %d: %.1fM frames/s (default %.1fM)" % (
+                name, rows, prec, best["waves_per_cu"], best["frames_per_s"] / 1e6,
                 best["default_frames_per_s"] / 1e6), flush=True)
 
 

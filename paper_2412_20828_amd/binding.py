@@ -88,7 +88,7 @@ def lib():
     L.bch_syndrome_check.argtypes = [P, P, i64, P, P]
     L.bch_quantize_llr.argtypes = [P, i64, i64, i32, ctypes.c_float, P, i64, P]
     L.bch_osd_decode.argtypes = [P, P, i64, i64, i32, P, P, i32]
-    L.bch_decoder_set_tuning.argtypes = [P, i32, i32]
+    L.bch_decoder_set_tuning.argtypes = [P, i32]
     L.bch_mixed_workspace_size.argtypes = [P, i32, i64]
     L.bch_mixed_workspace_size.restype = ctypes.c_size_t
     L.bch_mixed_decode_batch.argtypes = [P, i32, P, P, i64, i64, P, P, i64, P, P, P, ctypes.c_size_t, P]
@@ -206,10 +206,10 @@ class Decoder:
     def specialized(self) -> bool:
         return bool(lib().bch_decoder_is_specialized(self.h))
 
-    def set_tuning(self, range_frames: int = 0, waves_per_cu: int = 0):
-        """Frames per persistent-wave range and waves per CU (0: defaults)."""
-        _check(lib().bch_decoder_set_tuning(self.h, range_frames, waves_per_cu), "bch_decoder_set_tuning")
-        self.tuning = (range_frames, waves_per_cu)
+    def set_tuning(self, waves_per_cu: int = 0):
+        """Waves per CU of the persistent grid (0: the kernel's default)."""
+        _check(lib().bch_decoder_set_tuning(self.h, waves_per_cu), "bch_decoder_set_tuning")
+        self.tuning = waves_per_cu
 
     def workspace_size(self, F: int) -> int:
         return int(lib().bch_decode_workspace_size(self.h, F))

@@ -83,7 +83,7 @@ def build(verbose: bool = True, with_spec: bool = True) -> str:
     os.makedirs(gen_dir, exist_ok=True)
     # stage 1: empty specialisation table
     _write_if_changed(os.path.join(gen_dir, "spec_table.inc"),
-                      "static const SpecKernel kSpecKernels[] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n")
+                      "static const SpecKernel kSpecKernels[] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n")
     jobs = [(_compile_host, os.path.join(CSRC, s), gen_dir) for s in HOST_SRCS]
     with cf.ThreadPoolExecutor(max_workers=8) as ex:
         futs = [ex.submit(fn, src, inc) for fn, src, inc in jobs]

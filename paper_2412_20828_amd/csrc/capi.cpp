@@ -28,7 +28,6 @@ struct bch_decoder_s {
     uint32_t *d_gen = nullptr;  // [K][4] generator rows (device OSD)
     int msyn = 0;
     int n_cu = 0;
-    int range_frames = 256;
     int waves = 0;  // waves per CU of the persistent grid (0: the kernel's default)
     const bch::SpecKernel *spec = nullptr;
 };
@@ -98,21 +97,10 @@ static int waves_of(const bch_decoder_s *d)
     return d->waves > 0 ? d->waves : d->spec->waves_per_cu;
 }
 
-// frames per range of a decode of F frames: the configured size, lowered
-// (not below one wave's frames: 64, or 128 for the packed 16-bit kernels) so
-// that every persistent wave can get a range when the batch is small
-static int eff_range(const bch_decoder_s *d, int64_t F)
-{
-    const int64_t fw = d->spec->frames_per_wave;
-    const int64_t waves = std::max<int64_t>(1, (int64_t)d->n_cu * waves_of(d));
-    const int64_t r = F / waves / fw * fw;
-    return (int)std::max<int64_t>(fw, std::min<int64_t>(std::max<int64_t>(d->range_frames, fw), r));
-}
-
 // device workspace of one specialised decode of up to F frames
 static size_t spec_ws_bytes(const bch_decoder_s *d, int64_t F)
 {
-    size_t n = align256(bucket_ws_bytes(F, shift_period(d->N), eff_range(d, F)));
+    size_t n = align256(bucket_ws_bytes(F, shift_period(d->N)));
     if (d->spec->y_global)
         n += align256((size_t)d->n_cu * waves_of(d) * d->N * 64 * sizeof(float));
     return n;
@@ -126,9 +114,8 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
 {
     const int dp = shift_period(d->N);
     char *ws = static_cast<char *>(workspace);
-    const int range = eff_range(d, F);
-    BucketWs w = bucket_ws_carve(ws, F, dp, range);
-    hipError_t e = launch_bucketing(d_o, code_idx, code, F, dp, d->prm.n_branches > 1, range, w, stream);
+    BucketWs w = bucket_ws_carve(ws, F, dp);
+    hipError_t e = launch_bucketing(d_o, code_idx, code, F, dp, d->prm.n_branches > 1, w, stream);
     if (e != hipSuccess)
         return hip_fail(e, "bucketing prepass");
     SpecLaunch s{};
@@ -138,27 +125,23 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
     s.bcur = w.cursor;
     s.bend = w.end;
     s.n_buckets = d->prm.n_branches > 1 ? dp : 1;
-    s.ranges = w.ranges;
-    s.n_ranges = w.n_ranges;
-    s.range_counter = w.range_counter;
     s.bits = bits;
     s.bits_ld = bits_ld;
     s.iters = iters;
     s.flags = flags;
     s.trace = trace;
     s.yscratch = d->spec->y_global
-                     ? reinterpret_cast<float *>(ws + align256(bucket_ws_bytes(F, dp, range)))
+                     ? reinterpret_cast<float *>(ws + align256(bucket_ws_bytes(F, dp)))
                      : nullptr;
     s.max_iter = d->prm.max_iter;
     s.alpha = d->prm.alpha;
     // no more persistent waves than a batch of F frames can keep busy (small
-    // batches launch small grids): ceil(F / range) + dp ranges, or, for the
-    // kernels that hand out frames from per-bucket cursors, ceil(F / 64) + dp
+    // batches launch small grids): ceil(F / frames per workgroup) + dp
     // workgroups of wave_group waves
     const int64_t grid = (int64_t)d->n_cu * waves_of(d);
     const int g = d->spec->wave_group;
     const int64_t fw = d->spec->frames_per_wave;
-    const int64_t most = d->spec->cursor ? g * ((F + fw - 1) / fw + dp) : (F + range - 1) / range + dp;
+    const int64_t most = g * ((F + fw - 1) / fw + dp);
     if (most < grid)
         e = d->spec->launch(s, 1, (int)most, stream);
     else
@@ -510,15 +493,12 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
     return e == hipSuccess ? BCH_OK : hip_fail(e, "generic kernel launch");
 }
 
-int bch_decoder_set_tuning(bch_decoder dec, int range_frames, int waves_per_cu)
+int bch_decoder_set_tuning(bch_decoder dec, int waves_per_cu)
 {
     if (!dec)
         return fail(BCH_EINVAL, "decoder is NULL");
-    if (range_frames != 0 && (range_frames < 64 || range_frames > (1 << 20)))
-        return fail(BCH_EINVAL, "range_frames must be 0 or in [64, 2^20]");
     if (waves_per_cu < 0 || waves_per_cu > 16)
         return fail(BCH_EINVAL, "waves_per_cu must be in [0, 16]");
-    dec->range_frames = range_frames ? range_frames : 256;
     dec->waves = waves_per_cu;
     return BCH_OK;
 }

@@ -3,8 +3,7 @@
 // permutation.  Counting sort without global atomics:
 //   1. each block of BLK frames counts its frames per bucket;
 //   2. one workgroup scans the per-block counts bucket by bucket (bucket
-//      starts, per-block offsets) and cuts every bucket into ranges of at most
-//      range_frames frames;
+//      starts, per-block offsets, bucket slices [cursor, end));
 //   3. each block places its frames at its offsets plus their rank inside the
 //      block (LDS counters).
 // Frames keep their input order inside a (block, bucket) up to the LDS-atomic
@@ -47,13 +46,11 @@ __global__ void __launch_bounds__(TPB) bucket_count(const uint8_t *__restrict__ 
         blk_hist[(size_t)blockIdx.x * dp + threadIdx.x] = h[threadIdx.x];
 }
 
-// one workgroup: per-block offsets in bucket-major order, bucket starts, ranges
-__global__ void __launch_bounds__(SCAN) bucket_scan(int *__restrict__ blk_hist, int nblk, int dp,
-                                                    int range_frames, BucketWs w)
+// one workgroup: per-block offsets in bucket-major order, bucket slices
+__global__ void __launch_bounds__(SCAN) bucket_scan(int *__restrict__ blk_hist, int nblk, int dp, BucketWs w)
 {
     __shared__ int bucket_total[MAXB];
     __shared__ int bucket_start[MAXB];
-    __shared__ int range_start[MAXB + 1];
     const int tid = threadIdx.x;
     // one wave per bucket: exclusive prefix over the blocks, 64 blocks at a
     // time with a shuffle scan (no workgroup barriers inside)
@@ -79,30 +76,17 @@ __global__ void __launch_bounds__(SCAN) bucket_scan(int *__restrict__ blk_hist, 
     }
     __syncthreads();
     if (tid == 0) {
-        int start = 0, nr = 0;
+        int start = 0;
         for (int d = 0; d < dp; d++) {
             bucket_start[d] = start;
-            range_start[d] = nr;
             start += bucket_total[d];
-            nr += (bucket_total[d] + range_frames - 1) / range_frames;
         }
-        range_start[dp] = nr;
-        *w.n_ranges = nr;
-        *w.range_counter = 0;
     }
     __syncthreads();
     if (tid < dp) {
         w.counts[tid] = bucket_total[tid];
         w.cursor[tid] = bucket_start[tid];
         w.end[tid] = bucket_start[tid] + bucket_total[tid];
-    }
-    for (int d = 0; d < dp; d++) {
-        const int nr = range_start[d + 1] - range_start[d];
-        for (int r = tid; r < nr; r += SCAN) {
-            const int o = r * range_frames;
-            const int e = min(o + range_frames, bucket_total[d]);
-            w.ranges[range_start[d] + r] = make_int4(bucket_start[d] + o, bucket_start[d] + e, d, 0);
-        }
     }
 }
 
@@ -130,15 +114,14 @@ int64_t n_blocks(int64_t F) { return (F + BLK - 1) / BLK; }
 
 }  // namespace
 
-size_t bucket_ws_bytes(int64_t F, int dp, int range_frames)
+size_t bucket_ws_bytes(int64_t F, int dp)
 {
-    const size_t head = align16(sizeof(int) * (3 * (size_t)dp + 2));
-    const size_t nr = (size_t)(F / range_frames) + dp + 1;
+    const size_t head = align16(sizeof(int) * 3 * (size_t)dp);
     const size_t hist = align16(sizeof(int) * (size_t)n_blocks(F) * dp);
-    return head + nr * sizeof(int4) + hist + align16((size_t)F * sizeof(int));
+    return head + hist + align16((size_t)F * sizeof(int));
 }
 
-BucketWs bucket_ws_carve(void *ws, int64_t F, int dp, int range_frames)
+BucketWs bucket_ws_carve(void *ws, int64_t F, int dp)
 {
     BucketWs w;
     char *p = static_cast<char *>(ws);
@@ -146,11 +129,7 @@ BucketWs bucket_ws_carve(void *ws, int64_t F, int dp, int range_frames)
     w.counts = h;
     w.cursor = h + dp;
     w.end = h + 2 * dp;
-    w.n_ranges = h + 3 * dp;
-    w.range_counter = h + 3 * dp + 1;
-    p += align16(sizeof(int) * (3 * (size_t)dp + 2));
-    w.ranges = reinterpret_cast<int4 *>(p);
-    p += ((size_t)(F / range_frames) + dp + 1) * sizeof(int4);
+    p += align16(sizeof(int) * 3 * (size_t)dp);
     w.blk_hist = reinterpret_cast<int *>(p);
     p += align16(sizeof(int) * (size_t)n_blocks(F) * dp);
     w.order = reinterpret_cast<int *>(p);
@@ -158,14 +137,14 @@ BucketWs bucket_ws_carve(void *ws, int64_t F, int dp, int range_frames)
 }
 
 hipError_t launch_bucketing(const uint8_t *d_o, const uint8_t *code_idx, int code, int64_t F, int dp,
-                            int use_offsets, int range_frames, const BucketWs &w, hipStream_t stream)
+                            int use_offsets, const BucketWs &w, hipStream_t stream)
 {
     if (dp > MAXB || F <= 0)
         return hipErrorInvalidValue;
     const int nblk = (int)n_blocks(F);
     hipLaunchKernelGGL(bucket_count, dim3(nblk), dim3(TPB), 0, stream, d_o, code_idx, code, F, dp, use_offsets,
                        w.blk_hist);
-    hipLaunchKernelGGL(bucket_scan, dim3(1), dim3(SCAN), 0, stream, w.blk_hist, nblk, dp, range_frames, w);
+    hipLaunchKernelGGL(bucket_scan, dim3(1), dim3(SCAN), 0, stream, w.blk_hist, nblk, dp, w);
     hipLaunchKernelGGL(bucket_place, dim3(nblk), dim3(TPB), 0, stream, d_o, code_idx, code, F, dp, use_offsets,
                        w.blk_hist, w);
     return hipGetLastError();

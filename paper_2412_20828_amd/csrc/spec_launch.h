@@ -11,9 +11,6 @@ struct SpecLaunch {
     const void *llr;       // device [F][ld] float32 (FP32) or int8 (FIX8)
     int64_t ld;
     const int *order;      // frame indices grouped by d_o (bucketing prepass)
-    const int4 *ranges;    // {start, end, d_o, 0} slices of order
-    const int *n_ranges;
-    int *range_counter;    // next range to hand out (zeroed by the prepass)
     int *bcur;             // per bucket: next slot of order to hand out (atomic)
     const int *bend;       // per bucket: end of its slice of order
     int n_buckets;
@@ -28,25 +25,21 @@ struct SpecLaunch {
 };
 
 // Bucketing prepass: groups frames by random offset d_o (reduced modulo d_p;
-// all in bucket 0 for one branch) and cuts every bucket into ranges of at
-// most range_frames frames.  Bucket b is order[cursor[b], end[b]) once the
-// prepass is done; kernels that hand out frames one at a time advance
-// cursor[b] atomically.
+// all in bucket 0 for one branch).  Bucket b is order[cursor[b], end[b]) once
+// the prepass is done; the persistent kernels hand out its frames by
+// advancing cursor[b] atomically.
 struct BucketWs {
     int *counts;
     int *cursor;
     int *end;
-    int *n_ranges;
-    int *range_counter;
-    int4 *ranges;
     int *blk_hist;  // [blocks of 2048 frames][d_p] counts, then offsets
     int *order;
 };
 
-size_t bucket_ws_bytes(int64_t F, int dp, int range_frames);
-BucketWs bucket_ws_carve(void *ws, int64_t F, int dp, int range_frames);
+size_t bucket_ws_bytes(int64_t F, int dp);
+BucketWs bucket_ws_carve(void *ws, int64_t F, int dp);
 // code_idx (may be null): only frames with code_idx[f] == code are taken.
 hipError_t launch_bucketing(const uint8_t *d_o, const uint8_t *code_idx, int code, int64_t F, int dp,
-                            int use_offsets, int range_frames, const BucketWs &w, hipStream_t stream);
+                            int use_offsets, const BucketWs &w, hipStream_t stream);
 
 }  // namespace bch

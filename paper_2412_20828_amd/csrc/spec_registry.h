@@ -19,9 +19,8 @@ struct SpecKernel {
     int variant;       // 0, or 1 for the packed 16-bit fixed-point kernel
     int waves_per_cu;  // persistent grid = CUs x waves_per_cu wavefronts
     int y_global;      // 1: y lives in device scratch [grid][N][64] floats
-    int frames_per_wave;  // 64, or 128 for the packed 16-bit kernels
+    int frames_per_wave;  // frames per workgroup: 64, or 128 for the packed 16-bit kernels
     int wave_group;       // waves per workgroup: 1, or 3 when the branch types share 64 frames
-    int cursor;           // 1: frames handed out by per-bucket cursors, 0: by ranges
     const char *name;
     hipError_t (*launch)(const SpecLaunch &, int n_cu, int waves_per_cu, hipStream_t);
 };

@@ -313,9 +313,9 @@ def generate(stage1_lib: str, out_dir: str):
                                            "nms_spec_group.inc" if group else "nms_spec_fp32.inc"))
         srcs.append(src_path)
         decls.append("namespace %s { hipError_t launch(const SpecLaunch &, int, int, hipStream_t); }" % ns)
-        entries.append("    {0x%016xull, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, \"%s\", &%s::launch}," %
+        entries.append("    {0x%016xull, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, \"%s\", &%s::launch}," %
                        (fingerprint(H), N, M, B, mode, prec, variant, waves, 1 if N > 64 and not regacc else 0,
-                        128 if pk16 else 64, 3 if group else 1, 0 if pk16 else 1, ns, ns))
+                        128 if pk16 else 64, 3 if group else 1, ns, ns))
     table = "\n".join(decls) + "\nstatic const SpecKernel kSpecKernels[] = {\n" + "\n".join(entries) + \
-        "\n    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n"
+        "\n    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n"
     return srcs, table
