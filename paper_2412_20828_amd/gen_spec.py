@@ -36,6 +36,10 @@ SPECS = [
     ("bch63_45", 33, 1, 1, 0, 5),
     ("bch63_36", 122, 1, 1, 0, 4),
 ]
+# rows whose min1/min2 chains the one-wave-per-SIMD (N = 127) row functions
+# interleave (2 measured best: 4 gave 2% less)
+ILP_ROWS = 2
+
 CODE_DEFS = {
     "bch63_36": (6, 0b1000011, 5),
     "bch63_45": (6, 0b1000011, 3),
@@ -117,6 +121,68 @@ def _forward(cols):
         out.append("        u2 = med3u(u1, u2, __float_as_uint(A[%d])); u1 = min(u1, __float_as_uint(A[%d]));" % (c, c))
     out.append("        const float m1 = __uint_as_float(u1), m2 = __uint_as_float(u2);")
     return out
+
+
+def body_source_ilp(H: np.ndarray, fix8: bool = False, group: int = 2) -> str:
+    """The row function (accumulating form, FP32 or fixed point) with
+    independent work side by side, for kernels that run one wave per SIMD and
+    so have no other wave to issue while an instruction waits for its
+    predecessor: the min1/min2 chains of `group` consecutive rows interleaved
+    step by step, and the c2v selections of each row two edges at a time,
+    pinned by scheduling barriers.  Every column is still updated by its rows
+    in ascending order."""
+    M, N = H.shape
+    W32 = (N + 31) // 32
+    out = [_MED3U, "__device__ __forceinline__ void body(const float *__restrict__ A, "
+           "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
+    for j0 in range(0, M, group):
+        rows = list(range(j0, min(M, j0 + group)))
+        out.append("    { // rows %s" % ", ".join(map(str, rows)))
+        cols = {}
+        for r, j in enumerate(rows):
+            cs = [int(c) for c in np.nonzero(H[j])[0]]
+            cols[r] = cs
+            masks = [0] * W32
+            for c in cs:
+                masks[c // 32] |= 1 << (c % 32)
+            cnt = " + ".join("__builtin_popcount(S[%d] & 0x%08xu)" % (k, masks[k]) for k in range(W32) if masks[k])
+            out.append("        const float sg%d = __uint_as_float(0x3f800000u | ((%s) << 31));" % (r, cnt))
+            c0, c1 = cs[0], cs[1]
+            out.append("        uint32_t u1_%d = min(__float_as_uint(A[%d]), __float_as_uint(A[%d])), "
+                       "u2_%d = max(__float_as_uint(A[%d]), __float_as_uint(A[%d]));" % (r, c0, c1, r, c0, c1))
+        for k in range(2, max(len(c) for c in cols.values())):
+            for r in cols:
+                if k < len(cols[r]):
+                    c = cols[r][k]
+                    out.append("        u2_%d = med3u(u1_%d, u2_%d, __float_as_uint(A[%d])); "
+                               "u1_%d = min(u1_%d, __float_as_uint(A[%d]));" % (r, r, r, c, r, r, c))
+            out.append("        __builtin_amdgcn_sched_barrier(0);")
+        for r in cols:
+            out.append("        const float m1_%d = __uint_as_float(u1_%d), m2_%d = __uint_as_float(u2_%d);"
+                       % (r, r, r, r))
+            if fix8:
+                out.append("        const float q1_%d = floorf(__builtin_fmaf(m1_%d, 0.75f, 0.5f)), "
+                           "q2_%d = floorf(__builtin_fmaf(m2_%d, 0.75f, 0.5f));" % (r, r, r, r))
+                out.append("        const float K_%d = __builtin_fmaf(m1_%d, 128.0f, q2_%d);" % (r, r, r))
+            else:
+                out.append("        const float P_%d = m1_%d + m2_%d;" % (r, r, r))
+        for r in cols:
+            cs = cols[r]
+            for k in range(0, len(cs), 2):
+                pair = cs[k:k + 2]
+                for q, c in enumerate(pair):
+                    if fix8:
+                        sel = "__builtin_amdgcn_fmed3f(q1_%d, q2_%d, __builtin_fmaf(A[%d], -128.0f, K_%d))" % (
+                            r, r, c, r)
+                    else:
+                        sel = "__builtin_amdgcn_fmed3f(m1_%d, m2_%d, P_%d - A[%d])" % (r, r, r, c)
+                    out.append("        const float t%d_%d = %s;" % (r, k + q, sel))
+                for q, c in enumerate(pair):
+                    out.append("        T[%d] = __builtin_fmaf(sg%d, t%d_%d, T[%d]);" % (c, r, r, k + q, c))
+                out.append("        __builtin_amdgcn_sched_barrier(0);")
+        out.append("    }")
+    out.append("}")
+    return "\n".join(out)
 
 
 def body_source(H: np.ndarray, accumulate: bool = False) -> str:
@@ -299,7 +365,10 @@ def generate(stage1_lib: str, out_dir: str):
             if pk16:
                 fh.write(body_source_pk16(H, B))
             else:
-                fh.write(body_source_fix8(H, regacc) if prec else body_source(H, regacc))
+                if regacc and N > 64:
+                    fh.write(body_source_ilp(H, fix8=bool(prec), group=ILP_ROWS))
+                else:
+                    fh.write(body_source_fix8(H, regacc) if prec else body_source(H, regacc))
             fh.write("\n\n" + syndrome_source(Hs) + "\n")
         src_path = os.path.join(out_dir, ns + ".hip")
         with open(src_path, "w") as fh:
