@@ -8,7 +8,9 @@ cyclic shifts of y, pi_I y and pi_F y), restart message mode, alpha = 0.75, at
 most 8 iterations with syndrome stopping, FP32; 1,000,000 frames per Eb/N0
 point, Eb/N0 = 1.0, 1.5, ..., 6.0 dB; random information bits, BPSK over
 AWGN, LLR = 2y/sigma^2 (seeded synthetic frames, resident in HBM before the
-timed region).
+timed region).  Each code's 11 points go through one decode call (22,000,000
+frames per step in two calls); --launch point makes every point a call of its
+own.
 
 Other workloads (--workload): "fix127", BCH(127,64) and BCH(127,99) at
 2.0..5.0 dB, 4,000,000 frames per point, FP32 and int8 fixed point; "mixed",
@@ -61,16 +63,16 @@ WORKLOADS = {
 FIX_SCALE = 4.0
 
 # HBM traffic of the specialised decode kernels, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs at 1,000,000 frames per launch, each scaled by what the same
-# counter reads for a plain 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE
-# x 1.0).  It holds only for the kernel sources the counters were taken on
+# WRITE_SIZE runs of the default sweep (one call of 11,000,000 frames per code),
+# each scaled by what the same counter reads for a plain 1 GiB device copy
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  It holds only for the kernel sources the counters were taken on
 # (hash of the grouped kernel template and its rotation helpers, the launch
 # header and the row-function generator); any other build reports traffic
 # null.
 TRAFFIC_SRC_HASH = "90247bcef94e1583"
 TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written) bytes per frame
-    "spec_bch63_36_m122_b9": (305.81, 68.65),
-    "spec_bch63_45_m33_b9": (267.45, 54.97),
+    "spec_bch63_36_m122_b9": (303.84, 74.11),
+    "spec_bch63_45_m33_b9": (267.28, 69.71),
 }
 
 
@@ -132,36 +134,41 @@ class Item:
         self.sample = None    # () -> [(code name, llr rows, d_o, gpu words, gpu iters)] for the CPU leg
 
 
-def end_to_end(items, torch, stream):
-    """PCIe-inclusive rate of one launch: LLRs from pinned host memory to the
-    device, decode, decisions / iterations / flags back to pinned host memory,
-    timed with events on the decode stream (the first work item, whose
-    inputs are re-sent from a pinned copy)."""
+def end_to_end(items, frames, torch, stream):
+    """PCIe-inclusive rate of one decode call over the first `frames` frames of
+    the first work item: LLRs from pinned host memory to the device, decode,
+    decisions / iterations / flags back to pinned host memory, timed with
+    events on the decode stream."""
     it = items[0]
-    dev_in = it.inputs[0]
+    n = min(frames, it.frames)
+    dev_in = it.inputs[0][:n]
     host_in = torch.empty(dev_in.shape, dtype=dev_in.dtype, pin_memory=True)
     host_in.copy_(dev_in)
-    outs = it.outputs
+    outs = [o[:n] for o in it.outputs]
     host_out = [torch.empty(o.shape, dtype=o.dtype, pin_memory=True) for o in outs]
     a, b, c, d = (torch.cuda.Event(enable_timing=True) for _ in range(4))
     torch.cuda.synchronize()
     a.record(stream)
     dev_in.copy_(host_in, non_blocking=True)
     b.record(stream)
-    it.launch()
+    it.dec.decode_into(dev_in, it.inputs[1][:n], *outs, workspace=it.ws, stream=stream)
     c.record(stream)
     for h, o in zip(host_out, outs):
         h.copy_(o, non_blocking=True)
     d.record(stream)
     torch.cuda.synchronize()
     tot = a.elapsed_time(d) / 1e3
-    return {"launch": it.label, "frames": it.frames, "h2d_ms": a.elapsed_time(b), "decode_ms": b.elapsed_time(c),
-            "d2h_ms": c.elapsed_time(d), "frames_per_s": it.frames / tot,
+    return {"launch": it.label, "frames": n, "h2d_ms": a.elapsed_time(b), "decode_ms": b.elapsed_time(c),
+            "d2h_ms": c.elapsed_time(d), "frames_per_s": n / tot,
             "bytes_in": dev_in.numel() * dev_in.element_size(),
             "bytes_out": sum(o.numel() * o.element_size() for o in outs)}
 
 
 def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_base):
+    """Work items of a single-code sweep.  With --launch code (the default) the
+    frames of all Eb/N0 points of a code sit in one array and go through one
+    decode call per precision; the per-point statistics are read from slices
+    of its outputs.  With --launch point every point is a call of its own."""
     items, mats = [], {}
     for ci, (name, rows) in enumerate(codes):
         d = B.CODE_DEFS[name]
@@ -173,12 +180,20 @@ def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_ba
                                 flags=(B.FORCE_GENERIC if args.generic else 0) |
                                 (B.PACKED16 if args.packed16 and prec == "fix8" and code.N <= 64 else 0))
                 for prec in precisions}
-        for pi, e in enumerate(points):
-            llr, cw, d_o = gen_point(name, args.frames, e, seed=seed_base + 10 * ci + pi)
-            F = llr.shape[0]
-            cwp = pack(cw)
-            llr_d = torch.from_numpy(llr).to(dev)
-            d_o_d = torch.from_numpy(d_o).to(dev)
+        groups = [[pi] for pi in range(len(points))] if args.launch == "point" else [list(range(len(points)))]
+        for grp in groups:
+            F = args.frames * len(grp)
+            ld = 64 if code.N <= 64 else 128
+            llr_d = torch.empty((F, ld), dtype=torch.float32, device=dev)
+            d_o_d = torch.empty(F, dtype=torch.uint8, device=dev)
+            pts = []  # (Eb/N0, first frame, packed codewords, first 64 LLR rows, their d_o)
+            for j, pi in enumerate(grp):
+                llr, cw, d_o = gen_point(name, args.frames, points[pi], seed=seed_base + 10 * ci + pi)
+                f0 = j * args.frames
+                llr_d[f0:f0 + args.frames].copy_(torch.from_numpy(llr))
+                d_o_d[f0:f0 + args.frames].copy_(torch.from_numpy(d_o))
+                pts.append((points[pi], f0, pack(cw), llr[:64].copy(), d_o[:64].copy()))
+                del llr, cw, d_o
             for prec in precisions:
                 dec = decs[prec]
                 if prec == "fix8":
@@ -190,27 +205,35 @@ def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_ba
                 it = torch.empty(F, dtype=torch.uint8, device=dev)
                 fl = torch.empty(F, dtype=torch.uint8, device=dev)
                 ws = torch.empty(max(1, dec.workspace_size(F)), dtype=torch.uint8, device=dev)
-                item = Item("%s@%g" % (name, e), prec, F,
+                label = "%s@%s" % (name, "%g" % points[grp[0]] if len(grp) == 1 else
+                                   "%g:%g" % (points[grp[0]], points[grp[-1]]))
+                item = Item(label, prec, F,
                             lambda st=stream, dec=dec, inp=inp, d_o_d=d_o_d, bits=bits, it=it, fl=fl, ws=ws:
                             dec.decode_into(inp, d_o_d, bits, it, fl, workspace=ws, stream=st))
                 item.inputs, item.outputs = (inp, d_o_d), (bits, it, fl)
+                item.dec, item.ws = dec, ws
                 item.kernel = ("spec_%s_m%d_b9%s" % (name, pcm.M, "_fix8" if prec == "fix8" else "")
                                if dec.specialized else "generic_%s" % prec)
 
-                def stats(name=name, e=e, prec=prec, code=code, pcm=pcm, bits=bits, it=it, fl=fl, cwp=cwp):
-                    w = bits.cpu().numpy().view(np.uint64)
-                    iters = it.cpu().numpy().astype(np.int64)
-                    conv = fl.cpu().numpy().astype(bool)
-                    err = (w != cwp[:, :w.shape[1]]).any(1)
-                    nbit = int(np.bitwise_count(w ^ cwp[:, :w.shape[1]]).sum())
-                    pt = {"code": name, "precision": prec, "ebn0": e, "fer": float(err.mean()),
-                          "ber": nbit / (len(err) * code.N), "avg_iters": float(iters.mean()),
-                          "undetected": float((err & conv).mean())}
-                    ops = iters.sum() * alg_ops_per_iteration(code.N, code.K, pcm.M, pcm.E, 9)
-                    return [pt], float(ops), len(err) * code.K
+                def stats(name=name, prec=prec, code=code, pcm=pcm, bits=bits, it=it, fl=fl, pts=pts):
+                    W = bits.cpu().numpy().view(np.uint64)
+                    I = it.cpu().numpy().astype(np.int64)
+                    C = fl.cpu().numpy().astype(bool)
+                    out = []
+                    for e, f0, cwp, _, _ in pts:
+                        w, iters, conv = W[f0:f0 + len(cwp)], I[f0:f0 + len(cwp)], C[f0:f0 + len(cwp)]
+                        err = (w != cwp[:, :w.shape[1]]).any(1)
+                        nbit = int(np.bitwise_count(w ^ cwp[:, :w.shape[1]]).sum())
+                        out.append({"code": name, "precision": prec, "ebn0": e, "fer": float(err.mean()),
+                                    "ber": nbit / (len(err) * code.N), "avg_iters": float(iters.mean()),
+                                    "undetected": float((err & conv).mean())})
+                    ops = I.sum() * alg_ops_per_iteration(code.N, code.K, pcm.M, pcm.E, 9)
+                    return out, float(ops), len(I) * code.K
 
-                def sample(name=name, llr=llr[:64].copy(), d_o=d_o[:64].copy(), bits=bits, it=it):
-                    return [(name, llr, d_o, bits[:64].cpu().numpy().view(np.uint64), it[:64].cpu().numpy())]
+                def sample(name=name, bits=bits, it=it, pts=pts):
+                    W = bits.cpu().numpy().view(np.uint64)
+                    I = it.cpu().numpy()
+                    return [(name, l64, d64, W[f0:f0 + 64], I[f0:f0 + 64]) for _, f0, _, l64, d64 in pts]
                 item.stats, item.sample = stats, (sample if prec == "fp32" else None)
                 items.append(item)
             del llr_d
@@ -558,6 +581,8 @@ def main():
     ap.add_argument("--workload", default="sweep63", choices=sorted(WORKLOADS))
     ap.add_argument("--frames", type=int, default=0, help="frames per Eb/N0 point (0: the workload's)")
     ap.add_argument("--ebn0", type=str, default="", help="lo:hi:step dB (empty: the workload's)")
+    ap.add_argument("--launch", default="code", choices=["code", "point"],
+                    help="sweeps: one decode call per code over all its Eb/N0 points, or one per point")
     ap.add_argument("--cpu-seconds", type=float, default=30.0, help="budget of the CPU oracle leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--generic", action="store_true", help="force the generic (unspecialised) kernel")
@@ -667,7 +692,7 @@ def main():
     elapsed = start.elapsed_time(stop) / 1e3
     launch_ms = np.array([[a.elapsed_time(b) for a, b in evs] for evs in ev])  # [steps][launch]
 
-    e2e = end_to_end(items, torch, stream) if args.workload != "mixed" else None
+    e2e = end_to_end(items, args.frames, torch, stream) if args.workload != "mixed" else None
 
     per_point = []
     ops_total = 0.0
@@ -677,6 +702,7 @@ def main():
     for k, item in enumerate(items):
         pts, ops, info = item.stats()
         for p in pts:
+            p["launch"] = item.label      # the decode call that holds the point
             p["launch_ms"] = float(np.median(launch_ms[:, k]))
         per_point += pts
         ops_total += ops
@@ -712,8 +738,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if precisions == ["fp32"] else "f32+i8",
         "data": "synthetic",
-        "config": {"workload": "%s, %d frames per %s, Eb/N0 %s dB%s" % (
+        "config": {"workload": "%s, %d frames per %s, Eb/N0 %s dB%s%s" % (
                        wdesc, args.frames, "step" if args.workload == "mixed" else "point", ebn0_desc,
+                       "" if args.workload == "mixed" else
+                       ("; one decode call per code over all its points" if args.launch == "code" else
+                        "; one decode call per point"),
                        ", each launch replayed from a captured HIP graph" if args.graph else ""),
                    "frames_per_step": total_frames},
         "frames_per_s_by_precision": {p: frames_by_prec[p] / time_by_prec[p] for p in time_by_prec},
@@ -791,7 +820,8 @@ def cpu_baseline(samples, mats, budget_s, gpu_fps):
         n1 += l.shape[0]
     one = n1 / (time.time() - t1)
     return {"value": n / secs, "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": "%d frames (the first 64 frames of each of %d launches' codes, %d repeats), FP64 "
+            "sample": "%d frames (the first 64 frames of each of %d slices: an Eb/N0 point of a code, or "
+                      "a code of the mixed call; %d repeats), FP64 "
                       "min1/min2 oracle, same frames as the GPU" % (n, len(samples), reps),
             "seconds": secs, "gpu_over_cpu": gpu_fps / (n / secs),
             "one_core": {"value": one, "sample": "%d frames of %s" % (n1, name)},

@@ -45,8 +45,8 @@ def apply_cached(decoder, code_name: str, rows: int) -> bool:
 
 
 def default_frames(N: int) -> int:
-    """Batch size of the tuning runs: the per-launch frames of the sweep (N = 63)
-    and of the 127-bit workloads.  The best grid depends on it: a smaller batch
+    """Batch size of the tuning runs: the frames of one Eb/N0 point of the sweep
+    (N = 63) and of the 127-bit workloads.  The best grid depends on it: a smaller batch
     favours fewer resident frames, whose drain at the end of the launch is
     shorter."""
     return 1_000_000 if N <= 64 else 4_000_000

@@ -103,6 +103,67 @@ def test_full_size_batches_sampled(B, name, rows, F, ebn0):
     compare_with_oracle(words, it_h[idx], flg_h[idx], None, *res)
 
 
+@pytest.mark.parametrize("name,rows,per,grid,precision", [
+    ("bch63_36", 122, 1_000_000, (1.0, 6.0, 0.5), "fp32"),
+    ("bch127_64", 72, 4_000_000, (2.0, 5.0, 0.5), "fp32"),
+    ("bch127_64", 72, 4_000_000, (2.0, 5.0, 0.5), "fix8")])
+def test_sweep_in_one_call_sampled(B, name, rows, per, grid, precision):
+    """A whole Eb/N0 sweep of one code in a single decode call, as the
+    benchmark launches it by default: 11 x 1,000,000 frames for length 63 and
+    7 x 4,000,000 for length 127.  Every converged word must pass the syndrome
+    test; sampled frames of every point must equal the oracle (FP32: the
+    tolerance of compare_with_oracle; int8: bit-exact)."""
+    from concurrent.futures import ThreadPoolExecutor
+    c, p = lib_objects(B, name, rows)
+    oc = oracle_code(name)
+    H = oracle_hopt(name, rows)
+    lo, hi, st = grid
+    points = [lo + k * st for k in range(int(round((hi - lo) / st)) + 1)]
+    F = per * len(points)
+    ld = 64 if c.N <= 64 else 128
+    llr = torch.empty((F, ld), dtype=torch.float32, device="cuda")
+    d_o = torch.empty(F, dtype=torch.uint8, device="cuda")
+    blk = 500_000
+    jobs = [(j, e, k) for j, e in enumerate(points) for k in range(per // blk)]
+    with ThreadPoolExecutor(8) as ex:
+        for (j, e, k), q in zip(jobs, ex.map(lambda a: synth.frames(name, blk, a[1], seed=123 + a[0], block=a[2]),
+                                              jobs)):
+            f0 = j * per + k * blk
+            llr[f0:f0 + blk].copy_(torch.from_numpy(q.llr))
+            d_o[f0:f0 + blk].copy_(torch.from_numpy(q.d_o))
+    if precision == "fix8":
+        inp = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
+        B.quantize_llr(llr, c.N, 4.0, inp)
+        del llr
+        dec = B.Decoder(c, p, n_branches=9, max_iter=8, precision=B.FIX8)
+    else:
+        inp = llr
+        dec = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8)
+    assert dec.specialized
+    bits, iters, flg, _ = dec.decode(inp, d_o)
+    ok = torch.empty(F, dtype=torch.uint8, device="cuda")
+    B.syndrome_check(c, bits, ok)
+    torch.cuda.synchronize()
+    flg_h = flg.cpu().numpy()
+    it_h = iters.cpu().numpy()
+    assert np.array_equal(ok.cpu().numpy()[flg_h == 1], np.ones(int(flg_h.sum()), np.uint8))
+    assert it_h.min() >= 1 and it_h.max() <= 8 and (it_h[flg_h == 0] == 8).all()
+    rng = np.random.default_rng(17)
+    idx = np.sort(np.concatenate([j * per + rng.choice(per, 150, replace=False) for j in range(len(points))]))
+    x_h = inp[torch.from_numpy(idx).cuda()].cpu().numpy()
+    d_h = d_o.cpu().numpy()[idx]
+    words = B.unpack_bits(bits.cpu().numpy().view(np.uint64)[idx], c.N)
+    if precision == "fix8":
+        ow, oit, ocv = oracle.decode_batch(H, oc.Hstd, x_h, d_h, 9, 0.75, 8, oracle.R1,
+                                           kind=oracle.KIND_FIXED, threads=8)
+        assert np.array_equal(words, ow)
+        assert np.array_equal(it_h[idx], oit)
+        assert np.array_equal(flg_h[idx].astype(bool), ocv)
+    else:
+        res = oracle.decode_batch(H, oc.Hstd, x_h, d_h, 9, 0.75, 8, oracle.R1, threads=8, trace=True)
+        compare_with_oracle(words, it_h[idx], flg_h[idx], None, *res)
+
+
 @pytest.mark.parametrize("mode", [oracle.R2, oracle.R3])
 def test_enhanced_nms_memory_modes(B, mode):
     fr, g, o, _ = run_pair(B, "bch63_45", 33, 300, 3.0, 12, 9, mode, 6)
