@@ -69,10 +69,10 @@ FIX_SCALE = 4.0
 # (hash of the grouped kernel template and its rotation helpers, the launch
 # header and the row-function generator); any other build reports traffic
 # null.
-TRAFFIC_SRC_HASH = "90247bcef94e1583"
+TRAFFIC_SRC_HASH = "58c188f1e9661d87"
 TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written) bytes per frame
-    "spec_bch63_36_m122_b9": (303.84, 74.11),
-    "spec_bch63_45_m33_b9": (267.28, 69.71),
+    "spec_bch63_36_m122_b9": (302.84, 73.98),
+    "spec_bch63_45_m33_b9": (267.34, 69.17),
 }
 
 
@@ -178,7 +178,7 @@ def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_ba
         decs = {prec: B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8,
                                 precision=B.FIX8 if prec == "fix8" else B.FP32,
                                 flags=(B.FORCE_GENERIC if args.generic else 0) |
-                                (B.PACKED16 if args.packed16 and prec == "fix8" and code.N <= 64 else 0))
+                                (B.PACKED16 if args.packed16 and prec == "fix8" else 0))
                 for prec in precisions}
         groups = [[pi] for pi in range(len(points))] if args.launch == "point" else [list(range(len(points)))]
         for grp in groups:
@@ -212,7 +212,8 @@ def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_ba
                             dec.decode_into(inp, d_o_d, bits, it, fl, workspace=ws, stream=st))
                 item.inputs, item.outputs = (inp, d_o_d), (bits, it, fl)
                 item.dec, item.ws = dec, ws
-                item.kernel = ("spec_%s_m%d_b9%s" % (name, pcm.M, "_fix8" if prec == "fix8" else "")
+                item.kernel = ("spec_%s_m%d_b9%s" % (name, pcm.M, ("_fix8_pk16" if args.packed16 else "_fix8")
+                                                     if prec == "fix8" else "")
                                if dec.specialized else "generic_%s" % prec)
 
                 def stats(name=name, prec=prec, code=code, pcm=pcm, bits=bits, it=it, fl=fl, pts=pts):
@@ -257,7 +258,8 @@ def build_mixed(args, B, torch, dev, stream, codes, probs, lohi, precisions, see
     items = []
     for prec in precisions:
         decs = [B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8,
-                          precision=B.FIX8 if prec == "fix8" else B.FP32) for c, p in objs]
+                          precision=B.FIX8 if prec == "fix8" else B.FP32,
+                          flags=B.PACKED16 if args.packed16 and prec == "fix8" else 0) for c, p in objs]
         if args.tuned:
             from paper_2412_20828_amd import autotune
             for (name, rows), dec in zip(codes, decs):
@@ -589,7 +591,7 @@ def main():
     ap.add_argument("--tuned", action="store_true", help="apply the autotuner's cached launch shapes")
     ap.add_argument("--precision", default="", choices=["", "fp32", "fix8", "both"],
                     help="override the workload's precisions")
-    ap.add_argument("--packed16", action="store_true", help="fixed point: the packed 16-bit kernels (N = 63)")
+    ap.add_argument("--packed16", action="store_true", help="fixed point: the packed 16-bit kernels (two frames per lane)")
     ap.add_argument("--graph", action="store_true",
                     help="capture each launch of the step in a HIP graph once and replay it in the timed loop")
     ap.add_argument("--requests", type=int, default=3000, help="requests of the serving workload")

@@ -128,9 +128,10 @@ enum { BCH_MODE_RESTART = 1, BCH_MODE_MEMORY = 2, BCH_MODE_EXTRINSIC = 3 };
 enum { BCH_FP32 = 0, BCH_FIX8 = 1 };
 enum {
     BCH_DEC_FORCE_GENERIC = 1, /* do not use a PCM-specialised kernel */
-    BCH_DEC_PACKED16 = 2       /* BCH_FIX8 with N = 63: the packed 16-bit kernel (two frames
-                                  per lane, same results); without it the fixed-point kernel
-                                  holds its integers in 32-bit registers */
+    BCH_DEC_PACKED16 = 2       /* BCH_FIX8: the packed 16-bit kernel (two frames per lane,
+                                  same results), registered for the four workload matrices of
+                                  N = 63 and 127; without it the fixed-point kernel holds its
+                                  integers in 32-bit registers */
 };
 typedef struct {
     int n_branches; /* 1, 3 or 9 */

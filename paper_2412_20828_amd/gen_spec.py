@@ -30,6 +30,8 @@ SPECS = [
     # packed 16-bit fixed point, two frames per lane (opt-in variant)
     ("bch63_45", 33, 9, 1, 1, 8, 1),
     ("bch63_36", 122, 9, 1, 1, 8, 1),
+    ("bch127_99", 33, 9, 1, 1, 4, 1),
+    ("bch127_64", 72, 9, 1, 1, 4, 1),
     # branch-count ablation (one and three branches, restart mode)
     ("bch63_45", 33, 3, 1, 0, 8),
     ("bch63_36", 122, 3, 1, 0, 8),
@@ -354,12 +356,12 @@ def generate(stage1_lib: str, out_dir: str):
         ns = "spec_%s_m%d_b%d%s%s" % (name, M, B, "_fix8" if prec else "", "_pk16" if variant else "")
         body_path = os.path.join(out_dir, ns + "_body.inc")
         regacc = 1 if B > 1 else 0
-        pk16 = 1 if prec and regacc and N <= 64 and variant else 0
+        pk16 = 1 if prec and regacc and variant else 0
         # nine branches of a short code: three waves (one per automorphism
         # type) share each 64 frames
         group = 1 if regacc and N <= 64 and B == 9 and not pk16 else 0
         if variant and not pk16:
-            raise ValueError("the packed variant needs N <= 64, fixed point and 3 or 9 branches")
+            raise ValueError("the packed variant needs fixed point and 3 or 9 branches")
         with open(body_path, "w") as fh:
             fh.write("// generated: %s, H_o %d x %d, %d edges\n" % (name, M, N, int(H.sum())))
             if pk16:

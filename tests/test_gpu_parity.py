@@ -106,7 +106,8 @@ def test_full_size_batches_sampled(B, name, rows, F, ebn0):
 @pytest.mark.parametrize("name,rows,per,grid,precision", [
     ("bch63_36", 122, 1_000_000, (1.0, 6.0, 0.5), "fp32"),
     ("bch127_64", 72, 4_000_000, (2.0, 5.0, 0.5), "fp32"),
-    ("bch127_64", 72, 4_000_000, (2.0, 5.0, 0.5), "fix8")])
+    ("bch127_64", 72, 4_000_000, (2.0, 5.0, 0.5), "fix8"),
+    ("bch127_64", 72, 4_000_000, (2.0, 5.0, 0.5), "fix8_packed16")])
 def test_sweep_in_one_call_sampled(B, name, rows, per, grid, precision):
     """A whole Eb/N0 sweep of one code in a single decode call, as the
     benchmark launches it by default: 11 x 1,000,000 frames for length 63 and
@@ -131,11 +132,12 @@ def test_sweep_in_one_call_sampled(B, name, rows, per, grid, precision):
             f0 = j * per + k * blk
             llr[f0:f0 + blk].copy_(torch.from_numpy(q.llr))
             d_o[f0:f0 + blk].copy_(torch.from_numpy(q.d_o))
-    if precision == "fix8":
+    if precision.startswith("fix8"):
         inp = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
         B.quantize_llr(llr, c.N, 4.0, inp)
         del llr
-        dec = B.Decoder(c, p, n_branches=9, max_iter=8, precision=B.FIX8)
+        dec = B.Decoder(c, p, n_branches=9, max_iter=8, precision=B.FIX8,
+                        flags=B.PACKED16 if precision == "fix8_packed16" else 0)
     else:
         inp = llr
         dec = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8)
@@ -153,7 +155,7 @@ def test_sweep_in_one_call_sampled(B, name, rows, per, grid, precision):
     x_h = inp[torch.from_numpy(idx).cuda()].cpu().numpy()
     d_h = d_o.cpu().numpy()[idx]
     words = B.unpack_bits(bits.cpu().numpy().view(np.uint64)[idx], c.N)
-    if precision == "fix8":
+    if precision.startswith("fix8"):
         ow, oit, ocv = oracle.decode_batch(H, oc.Hstd, x_h, d_h, 9, 0.75, 8, oracle.R1,
                                            kind=oracle.KIND_FIXED, threads=8)
         assert np.array_equal(words, ow)
@@ -335,7 +337,8 @@ def run_fix8_pair(B, name, rows, F, ebn0, seed, scale=4.0, flags=0):
 
 @pytest.mark.parametrize("name,ebn0,packed", [("bch63_45", 3.0, False), ("bch63_36", 3.5, False),
                                               ("bch63_45", 3.0, True), ("bch63_36", 3.5, True),
-                                              ("bch127_99", 4.0, False), ("bch127_64", 3.5, False)])
+                                              ("bch127_99", 4.0, False), ("bch127_64", 3.5, False),
+                                              ("bch127_99", 4.0, True), ("bch127_64", 3.5, True)])
 def test_fixed_point_bit_exact(B, name, ebn0, packed):
     """int8 messages, (3m+2)>>2 c2v magnitudes, integer branch average:
     identical decoded words, iteration counts, flags and every per-iteration
@@ -352,10 +355,12 @@ def test_fixed_point_bit_exact(B, name, ebn0, packed):
         assert np.array_equal(tr[f, :oit[f], :N], otr[f, :oit[f]]), f
 
 
+@pytest.mark.parametrize("packed", [False, True])
 @pytest.mark.parametrize("name,rows", [("bch127_64", 72), ("bch127_99", 33)])
-def test_fixed_point_full_size_sampled(B, name, rows):
+def test_fixed_point_full_size_sampled(B, name, rows, packed):
     """4,000,000 frames per point in one launch; 1000 sampled frames checked
-    bit-exactly against the integer oracle."""
+    bit-exactly against the integer oracle (also for the packed 16-bit
+    kernel)."""
     c, p = lib_objects(B, name, rows)
     oc = oracle_code(name)
     H = oracle_hopt(name, rows)
@@ -366,7 +371,8 @@ def test_fixed_point_full_size_sampled(B, name, rows):
     q = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
     B.quantize_llr(llr, c.N, 4.0, q)
     del llr
-    dec = B.Decoder(c, p, n_branches=9, max_iter=8, precision=B.FIX8)
+    dec = B.Decoder(c, p, n_branches=9, max_iter=8, precision=B.FIX8, flags=B.PACKED16 if packed else 0)
+    assert dec.specialized
     bits, iters, flg, _ = dec.decode(q, torch.from_numpy(d_o_h).cuda())
     torch.cuda.synchronize()
     idx = np.sort(np.random.default_rng(3).choice(F, 1000, replace=False))
