@@ -128,10 +128,15 @@ enum { BCH_MODE_RESTART = 1, BCH_MODE_MEMORY = 2, BCH_MODE_EXTRINSIC = 3 };
 enum { BCH_FP32 = 0, BCH_FIX8 = 1 };
 enum {
     BCH_DEC_FORCE_GENERIC = 1, /* do not use a PCM-specialised kernel */
-    BCH_DEC_PACKED16 = 2       /* BCH_FIX8: the packed 16-bit kernel (two frames per lane,
+    BCH_DEC_PACKED16 = 2,      /* BCH_FIX8: the packed 16-bit kernel (two frames per lane,
                                   same results), registered for the four workload matrices of
                                   N = 63 and 127; without it the fixed-point kernel holds its
                                   integers in 32-bit registers */
+    BCH_DEC_SMALL_ALWAYS = 4,  /* N = 127: always use the small-batch kernel (the nine
+                                  branches of 64 frames on three waves) where registered */
+    BCH_DEC_SMALL_NEVER = 8    /* N = 127: never use it.  Without either flag a decode of at
+                                  most 128 frames per CU uses it, a larger one the kernel
+                                  of one wave per 64 frames; the results are the same */
 };
 typedef struct {
     int n_branches; /* 1, 3 or 9 */
@@ -149,6 +154,10 @@ int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params,
                        bch_decoder *out);
 /* 1 if the decoder runs a PCM-specialised kernel, 0 for the generic one. */
 int bch_decoder_is_specialized(bch_decoder dec);
+/* Name of the kernel a decode of F frames runs ("generic" for the generic
+ * kernel, "" for a null decoder); the string is static and owned by the
+ * library. */
+const char *bch_decoder_kernel_name(bch_decoder dec, int64_t F);
 void bch_decoder_destroy(bch_decoder dec);
 
 /* Device workspace (bytes) a decode of F frames needs (0 for some configs). */

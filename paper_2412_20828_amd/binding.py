@@ -22,11 +22,14 @@ MODE_RESTART, MODE_MEMORY, MODE_EXTRINSIC = 1, 2, 3
 FP32, FIX8 = 0, 1
 FORCE_GENERIC = 1
 PACKED16 = 2
+SMALL_ALWAYS = 4
+SMALL_NEVER = 8
 
 SYMBOLS = [
     "bch_last_error", "bch_load_code", "bch_code_info", "bch_code_export", "bch_code_destroy",
     "bch_build_pcm", "bch_pcm_from_dense", "bch_pcm_info", "bch_pcm_export", "bch_pcm_destroy",
     "bch_make_automorphisms", "bch_decoder_create", "bch_decoder_is_specialized",
+    "bch_decoder_kernel_name",
     "bch_decoder_destroy", "bch_decode_workspace_size", "bch_nms_decode_batch",
     "bch_syndrome_check", "bch_quantize_llr", "bch_osd_decode", "bch_decoder_set_tuning",
     "bch_mixed_workspace_size", "bch_mixed_decode_batch", "bch_osd_decode_device", "bch_mixed_osd_decode",
@@ -80,6 +83,8 @@ def lib():
     L.bch_make_automorphisms.argtypes = [i32, i32, i32, P]
     L.bch_decoder_create.argtypes = [P, P, ctypes.POINTER(DecParams), P]
     L.bch_decoder_is_specialized.argtypes = [P]
+    L.bch_decoder_kernel_name.argtypes = [P, ctypes.c_int64]
+    L.bch_decoder_kernel_name.restype = ctypes.c_char_p
     L.bch_decoder_destroy.argtypes = [P]
     L.bch_decoder_destroy.restype = None
     L.bch_decode_workspace_size.argtypes = [P, i64]
@@ -205,6 +210,10 @@ class Decoder:
     @property
     def specialized(self) -> bool:
         return bool(lib().bch_decoder_is_specialized(self.h))
+
+    def kernel_name(self, F):
+        """Name of the kernel a decode of F frames runs."""
+        return lib().bch_decoder_kernel_name(self.h, F).decode()
 
     def set_tuning(self, waves_per_cu: int = 0):
         """Waves per CU of the persistent grid (0: the kernel's default)."""

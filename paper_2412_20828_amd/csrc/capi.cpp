@@ -29,7 +29,8 @@ struct bch_decoder_s {
     int msyn = 0;
     int n_cu = 0;
     int waves = 0;  // waves per CU of the persistent grid (0: the kernel's default)
-    const bch::SpecKernel *spec = nullptr;
+    const bch::SpecKernel *spec = nullptr;        // throughput kernel
+    const bch::SpecKernel *spec_small = nullptr;  // small-batch kernel (N = 127), or null
 };
 
 namespace bch {
@@ -97,6 +98,18 @@ static int waves_of(const bch_decoder_s *d)
     return d->waves > 0 ? d->waves : d->spec->waves_per_cu;
 }
 
+// the kernel of a decode of F frames: the small-batch kernel (three waves per
+// 64 frames) when it is registered and F gives each CU at most 128 frames
+// (measured on the 127-bit codes: 2.7x faster up to 64 frames per CU, 1.2x at
+// 128, 0.9x at 256), or when the decoder asks for it always; else the
+// throughput kernel
+static const bch::SpecKernel *spec_for(const bch_decoder_s *d, int64_t F)
+{
+    if (d->spec_small && ((d->prm.flags & BCH_DEC_SMALL_ALWAYS) || F <= (int64_t)d->n_cu * 128))
+        return d->spec_small;
+    return d->spec;
+}
+
 // device workspace of one specialised decode of up to F frames
 static size_t spec_ws_bytes(const bch_decoder_s *d, int64_t F)
 {
@@ -137,15 +150,18 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
     s.alpha = d->prm.alpha;
     // no more persistent waves than a batch of F frames can keep busy (small
     // batches launch small grids): ceil(F / frames per workgroup) + dp
-    // workgroups of wave_group waves
-    const int64_t grid = (int64_t)d->n_cu * waves_of(d);
-    const int g = d->spec->wave_group;
-    const int64_t fw = d->spec->frames_per_wave;
+    // workgroups of wave_group waves.  The tuned waves per CU belong to the
+    // throughput kernel.
+    const bch::SpecKernel *k = spec_for(d, F);
+    const int waves = k == d->spec ? waves_of(d) : k->waves_per_cu;
+    const int64_t grid = (int64_t)d->n_cu * waves;
+    const int g = k->wave_group;
+    const int64_t fw = k->frames_per_wave;
     const int64_t most = g * ((F + fw - 1) / fw + dp);
     if (most < grid)
-        e = d->spec->launch(s, 1, (int)most, stream);
+        e = k->launch(s, 1, (int)most, stream);
     else
-        e = d->spec->launch(s, d->n_cu, waves_of(d), stream);
+        e = k->launch(s, d->n_cu, waves, stream);
     return e == hipSuccess ? BCH_OK : hip_fail(e, "specialised kernel launch");
 }
 
@@ -396,8 +412,12 @@ int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params,
         bch_decoder_destroy(d);
         return hip_fail(he, "decoder tables");
     }
-    if (!(q.flags & BCH_DEC_FORCE_GENERIC))
-        d->spec = find_spec_kernel(p, q);
+    if (!(q.flags & BCH_DEC_FORCE_GENERIC)) {
+        const bool packed = (q.flags & BCH_DEC_PACKED16) != 0;
+        d->spec = find_spec_kernel(p, q, packed ? 1 : 0);
+        if (d->spec && !packed && !(q.flags & BCH_DEC_SMALL_NEVER))
+            d->spec_small = find_spec_kernel(p, q, 2);
+    }
     if (hipDeviceGetAttribute(&d->n_cu, hipDeviceAttributeMultiprocessorCount, d->dev) != hipSuccess ||
         d->n_cu <= 0)
         d->n_cu = 256;
@@ -406,6 +426,13 @@ int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params,
 }
 
 int bch_decoder_is_specialized(bch_decoder dec) { return dec && dec->spec ? 1 : 0; }
+
+const char *bch_decoder_kernel_name(bch_decoder dec, int64_t F)
+{
+    if (!dec)
+        return "";
+    return dec->spec ? spec_for(dec, F)->name : "generic";
+}
 
 void bch_decoder_destroy(bch_decoder dec)
 {

@@ -25,13 +25,12 @@ uint64_t pcm_fingerprint(const Pcm &p)
 
 #include "spec_table.inc"
 
-const SpecKernel *find_spec_kernel(const Pcm &p, const bch_dec_params &q)
+const SpecKernel *find_spec_kernel(const Pcm &p, const bch_dec_params &q, int variant)
 {
     const uint64_t fp = pcm_fingerprint(p);
     for (const SpecKernel &k : kSpecKernels) {
         if (k.launch == nullptr)
             continue;
-        const int variant = (q.flags & BCH_DEC_PACKED16) ? 1 : 0;
         if (k.fingerprint == fp && k.N == p.N && k.M == p.M && k.B == q.n_branches &&
             k.mode == q.mode && k.precision == q.precision && k.variant == variant)
             return &k;

@@ -16,7 +16,7 @@ namespace bch {
 struct SpecKernel {
     uint64_t fingerprint;  // of the matrix rows, see pcm_fingerprint()
     int N, M, B, mode, precision;
-    int variant;       // 0, or 1 for the packed 16-bit fixed-point kernel
+    int variant;       // 0; 1: packed 16-bit fixed point; 2: three waves per 64 frames, N = 127 (small batches)
     int waves_per_cu;  // persistent grid = CUs x waves_per_cu wavefronts
     int y_global;      // 1: y lives in device scratch [grid][N][64] floats
     int frames_per_wave;  // frames per workgroup: 64, or 128 for the packed 16-bit kernels
@@ -26,6 +26,6 @@ struct SpecKernel {
 };
 
 uint64_t pcm_fingerprint(const Pcm &p);
-const SpecKernel *find_spec_kernel(const Pcm &p, const bch_dec_params &q);
+const SpecKernel *find_spec_kernel(const Pcm &p, const bch_dec_params &q, int variant);
 
 }  // namespace bch

@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 # (code name, target rows of H_o, n_branches, mode, precision (0 FP32, 1 FIX8),
-#  waves per CU of the persistent grid[, variant: 1 = packed 16-bit fixed point])
+#  waves per CU of the persistent grid[, variant: 1 = packed 16-bit fixed point,
+#  2 = three waves per 64 frames for N = 127, the kernel for small batches])
 SPECS = [
     ("bch63_45", 33, 9, 1, 0, 12),
     ("bch63_36", 122, 9, 1, 0, 12),
@@ -32,6 +33,13 @@ SPECS = [
     ("bch63_36", 122, 9, 1, 1, 8, 1),
     ("bch127_99", 33, 9, 1, 1, 4, 1),
     ("bch127_64", 72, 9, 1, 1, 4, 1),
+    # small batches of the 127-bit codes: the branch types of 64 frames on
+    # three waves (one workgroup per CU)
+    ("bch127_99", 33, 9, 1, 0, 3, 2),
+    ("bch127_64", 72, 9, 1, 0, 3, 2),
+    ("bch127_78", 57, 9, 1, 0, 3, 2),
+    ("bch127_99", 33, 9, 1, 1, 3, 2),
+    ("bch127_64", 72, 9, 1, 1, 3, 2),
     # branch-count ablation (one and three branches, restart mode)
     ("bch63_45", 33, 3, 1, 0, 8),
     ("bch63_36", 122, 3, 1, 0, 8),
@@ -353,15 +361,18 @@ def generate(stage1_lib: str, out_dir: str):
             mats[(name, rows)] = _matrices(lib, name, rows)
         H, Hs = mats[(name, rows)]
         M, N = H.shape
-        ns = "spec_%s_m%d_b%d%s%s" % (name, M, B, "_fix8" if prec else "", "_pk16" if variant else "")
+        ns = "spec_%s_m%d_b%d%s%s" % (name, M, B, "_fix8" if prec else "",
+                                       {0: "", 1: "_pk16", 2: "_grp"}[variant])
         body_path = os.path.join(out_dir, ns + "_body.inc")
         regacc = 1 if B > 1 else 0
-        pk16 = 1 if prec and regacc and variant else 0
-        # nine branches of a short code: three waves (one per automorphism
-        # type) share each 64 frames
-        group = 1 if regacc and N <= 64 and B == 9 and not pk16 else 0
-        if variant and not pk16:
+        pk16 = 1 if prec and regacc and variant == 1 else 0
+        # nine branches: three waves (one per automorphism type) share each 64
+        # frames; always for N = 63, as the small-batch kernel for N = 127
+        group = 1 if regacc and B == 9 and ((N <= 64 and variant == 0) or variant == 2) else 0
+        if variant == 1 and not pk16:
             raise ValueError("the packed variant needs fixed point and 3 or 9 branches")
+        if variant == 2 and not (group and N > 64):
+            raise ValueError("the small-batch variant is for nine branches and N = 127")
         with open(body_path, "w") as fh:
             fh.write("// generated: %s, H_o %d x %d, %d edges\n" % (name, M, N, int(H.sum())))
             if pk16:
@@ -380,6 +391,8 @@ def generate(stage1_lib: str, out_dir: str):
                      "#define SPEC_Y_GLOBAL %d\n#define SPEC_FIX8 %d\n#define SPEC_REGACC %d\n"
                      % (N, B, ns, waves, yg, prec, regacc))
             fh.write('#define SPEC_BODY "%s"\n' % os.path.basename(body_path))
+            if group and N > 64:
+                fh.write("#define SPEC_WAVES_PER_SIMD 1\n")
             fh.write('#include "%s"\n' % ("nms_spec_pk16.inc" if pk16 else
                                            "nms_spec_group.inc" if group else "nms_spec_fp32.inc"))
         srcs.append(src_path)

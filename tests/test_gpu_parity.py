@@ -61,6 +61,82 @@ def test_enhanced_nms_restart_mode(B, name, ebn0, generic):
     compare_with_oracle(*g, *o, onestep=dec.onestep)
 
 
+def test_small_batch_kernel_selection(B):
+    """N = 127: decodes of at most 128 frames per CU run the three-wave kernel,
+    larger ones the kernel of one wave per 64 frames; the flags force either.
+    N = 63 has the three-wave kernel only."""
+    c, p = lib_objects(B, "bch127_64", 72)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    dec = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8)
+    assert dec.kernel_name(128 * n_cu) == "spec_bch127_64_m72_b9_grp"
+    assert dec.kernel_name(128 * n_cu + 1) == "spec_bch127_64_m72_b9"
+    always = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8, flags=B.SMALL_ALWAYS)
+    assert always.kernel_name(10 ** 7) == "spec_bch127_64_m72_b9_grp"
+    never = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8, flags=B.SMALL_NEVER)
+    assert never.kernel_name(100) == "spec_bch127_64_m72_b9"
+    packed = B.Decoder(c, p, n_branches=9, max_iter=8, precision=B.FIX8, flags=B.PACKED16)
+    assert packed.kernel_name(100) == "spec_bch127_64_m72_b9_fix8_pk16"
+    c63, p63 = lib_objects(B, "bch63_36", 122)
+    d63 = B.Decoder(c63, p63, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8)
+    assert d63.kernel_name(100) == d63.kernel_name(10 ** 7) == "spec_bch63_36_m122_b9"
+    gen = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8, flags=B.FORCE_GENERIC)
+    assert gen.kernel_name(100) == "generic"
+
+
+@pytest.mark.parametrize("flags", ["SMALL_ALWAYS", "SMALL_NEVER"])
+@pytest.mark.parametrize("name,ebn0", [("bch127_99", 4.0), ("bch127_64", 4.0), ("bch127_78", 4.0)])
+def test_127_kernels_both_forms(B, name, ebn0, flags):
+    """Both N = 127 kernels (three waves per 64 frames, and one) against the
+    oracle on several waves and a ragged tail."""
+    F = 64 * 7 + 37
+    fr, g, o, dec = run_pair(B, name, HO_ROWS[name], F, ebn0, 13, 9, oracle.R1, 8, flags=getattr(B, flags))
+    assert dec.kernel_name(F).endswith("_grp") == (flags == "SMALL_ALWAYS")
+    compare_with_oracle(*g, *o, onestep=dec.onestep)
+
+
+@pytest.mark.parametrize("flags", ["SMALL_ALWAYS", "SMALL_NEVER"])
+@pytest.mark.parametrize("name,ebn0", [("bch127_99", 4.0), ("bch127_64", 3.5)])
+def test_127_fixed_point_both_forms(B, name, ebn0, flags):
+    """Both N = 127 fixed-point kernels bit-exact against the integer oracle,
+    every frame, iteration count and per-iteration posterior."""
+    F = 64 * 5 + 29
+    fr, w, it, fl, tr, ow, oit, ocv, otr = run_fix8_pair(B, name, HO_ROWS[name], F, ebn0, 43,
+                                                         flags=getattr(B, flags))
+    assert np.array_equal(w, ow)
+    assert np.array_equal(it, oit)
+    assert np.array_equal(fl.astype(bool), ocv)
+    for f in range(F):
+        assert np.array_equal(tr[f, :oit[f], :w.shape[1]], otr[f, :oit[f]]), f
+
+
+def test_small_batch_kernel_large_batch_sampled(B):
+    """The three-wave N = 127 kernel forced onto a batch of 400,000 frames
+    (many frames per lane, every bucket drained): sampled frames against the
+    oracle, and every converged word passes the syndrome test."""
+    name, rows, F = "bch127_64", 72, 400_000
+    c, p = lib_objects(B, name, rows)
+    oc = oracle_code(name)
+    H = oracle_hopt(name, rows)
+    dec = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8, flags=B.SMALL_ALWAYS)
+    assert dec.kernel_name(F).endswith("_grp")
+    parts = [synth.frames(name, F // 4, 3.5, seed=88, block=k) for k in range(4)]
+    llr = torch.from_numpy(np.concatenate([q.llr for q in parts])).cuda()
+    d_o = torch.from_numpy(np.concatenate([q.d_o for q in parts])).cuda()
+    bits, iters, flg, _ = dec.decode(llr, d_o)
+    ok = torch.empty(F, dtype=torch.uint8, device="cuda")
+    B.syndrome_check(c, bits, ok)
+    torch.cuda.synchronize()
+    flg_h = flg.cpu().numpy()
+    it_h = iters.cpu().numpy()
+    assert np.array_equal(ok.cpu().numpy()[flg_h == 1], np.ones(int(flg_h.sum()), np.uint8))
+    assert it_h.min() >= 1 and it_h.max() <= 8 and (it_h[flg_h == 0] == 8).all()
+    idx = np.sort(np.random.default_rng(9).choice(F, 800, replace=False))
+    res = oracle.decode_batch(H, oc.Hstd, llr[torch.from_numpy(idx).cuda()].cpu().numpy(), d_o.cpu().numpy()[idx],
+                              9, 0.75, 8, oracle.R1, threads=8, trace=True)
+    words = B.unpack_bits(bits.cpu().numpy().view(np.uint64)[idx], c.N)
+    compare_with_oracle(words, it_h[idx], flg_h[idx], None, *res)
+
+
 @pytest.mark.parametrize("F", [1, 2, 63, 64, 65, 300])
 def test_specialised_small_and_ragged_batches(B, F):
     fr, g, o, dec = run_pair(B, "bch63_45", 33, F, 2.0, 30 + F, 9, oracle.R1, 8)
