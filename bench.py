@@ -164,6 +164,19 @@ def end_to_end(items, frames, torch, stream):
             "bytes_out": sum(o.numel() * o.element_size() for o in outs)}
 
 
+def make_decoder(args, B, code, pcm, name, rows, prec):
+    """Nine-branch restart-mode decoder of the workloads: the defaults, the
+    packed 16-bit layout (--packed16), the generic kernel (--generic), or the
+    autotuner's cached layout and grid (--tuned)."""
+    precision = B.FIX8 if prec == "fix8" else B.FP32
+    flags = (B.FORCE_GENERIC if args.generic else 0) | (B.PACKED16 if args.packed16 and prec == "fix8" else 0)
+    if args.tuned and not args.generic:
+        from paper_2412_20828_amd import autotune
+        return autotune.tuned_decoder(code, pcm, name, rows, precision=precision, flags=flags)
+    return B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8,
+                     precision=precision, flags=flags)
+
+
 def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_base):
     """Work items of a single-code sweep.  With --launch code (the default) the
     frames of all Eb/N0 points of a code sit in one array and go through one
@@ -175,11 +188,7 @@ def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_ba
         code = B.Code(d.m, d.prim, d.t)
         pcm = B.Pcm.build(code, target_rows=rows, seed=1)
         mats[name] = pcm
-        decs = {prec: B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8,
-                                precision=B.FIX8 if prec == "fix8" else B.FP32,
-                                flags=(B.FORCE_GENERIC if args.generic else 0) |
-                                (B.PACKED16 if args.packed16 and prec == "fix8" else 0))
-                for prec in precisions}
+        decs = {prec: make_decoder(args, B, code, pcm, name, rows, prec) for prec in precisions}
         groups = [[pi] for pi in range(len(points))] if args.launch == "point" else [list(range(len(points)))]
         for grp in groups:
             F = args.frames * len(grp)
@@ -212,9 +221,7 @@ def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_ba
                             dec.decode_into(inp, d_o_d, bits, it, fl, workspace=ws, stream=st))
                 item.inputs, item.outputs = (inp, d_o_d), (bits, it, fl)
                 item.dec, item.ws = dec, ws
-                item.kernel = ("spec_%s_m%d_b9%s" % (name, pcm.M, ("_fix8_pk16" if args.packed16 else "_fix8")
-                                                     if prec == "fix8" else "")
-                               if dec.specialized else "generic_%s" % prec)
+                item.kernel = dec.kernel_name(F) if dec.specialized else "generic_%s" % prec
 
                 def stats(name=name, prec=prec, code=code, pcm=pcm, bits=bits, it=it, fl=fl, pts=pts):
                     W = bits.cpu().numpy().view(np.uint64)
@@ -257,13 +264,7 @@ def build_mixed(args, B, torch, dev, stream, codes, probs, lohi, precisions, see
     ci_d = torch.from_numpy(ci).to(dev)
     items = []
     for prec in precisions:
-        decs = [B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8,
-                          precision=B.FIX8 if prec == "fix8" else B.FP32,
-                          flags=B.PACKED16 if args.packed16 and prec == "fix8" else 0) for c, p in objs]
-        if args.tuned:
-            from paper_2412_20828_amd import autotune
-            for (name, rows), dec in zip(codes, decs):
-                autotune.apply_cached(dec, name, rows)
+        decs = [make_decoder(args, B, c, p, name, rows, prec) for (c, p), (name, rows) in zip(objs, codes)]
         mix = B.MixedDecoder(decs)
         if prec == "fix8":
             inp = torch.empty(llr_d.shape, dtype=torch.int8, device=dev)
@@ -588,7 +589,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=30.0, help="budget of the CPU oracle leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--generic", action="store_true", help="force the generic (unspecialised) kernel")
-    ap.add_argument("--tuned", action="store_true", help="apply the autotuner's cached launch shapes")
+    ap.add_argument("--tuned", action="store_true",
+                    help="apply the autotuner's cached layouts (frames per wave) and grids")
     ap.add_argument("--precision", default="", choices=["", "fp32", "fix8", "both"],
                     help="override the workload's precisions")
     ap.add_argument("--packed16", action="store_true", help="fixed point: the packed 16-bit kernels (two frames per lane)")

@@ -1,12 +1,15 @@
 """Autotuner of the specialised decoders' launch shape.
 
-Knob: waves per CU of the persistent grid (the frames per workgroup are fixed
-by the kernel: 64 per one-wave workgroup and per three-wave group of the
-nine-branch N = 63 kernels, 128 for the packed 16-bit kernels).  The tuner
-times every candidate on a synthetic batch of the decoder's own code at a
-given Eb/N0 and keeps the fastest; results are cached in tuning.json beside
-this file, keyed by (code, rows of H_o, precision, branches, GPU name), and
-applied by apply_cached().
+Knobs:
+  - frames per wave of the fixed-point decoders: 64 (integers held in 32-bit
+    registers) or 128 (the packed 16-bit kernels, two frames per lane);
+  - waves per CU of the persistent grid.
+The tuner times every candidate on a synthetic batch of the decoder's own
+code at a given Eb/N0, at the size of the benchmark's decode calls, and keeps
+the fastest; results are cached in tuning.json beside this file, keyed by
+(code, rows of H_o, precision, branches, GPU name).  tuned_decoder() builds a
+decoder with the cached layout and grid; apply_cached() sets the grid of an
+existing decoder.
 """
 from __future__ import annotations
 
@@ -37,38 +40,79 @@ def load():
 
 
 def apply_cached(decoder, code_name: str, rows: int) -> bool:
+    """Set the cached grid of an existing decoder (only when its layout is the
+    cached one)."""
+    from . import binding as B
     entry = load().get(key(code_name, rows, decoder.precision, decoder.n_branches, _gpu_name()))
     if not entry or not decoder.specialized:
+        return False
+    if bool(entry.get("packed16", False)) != bool(decoder.flags & B.PACKED16):
         return False
     decoder.set_tuning(entry["waves_per_cu"])
     return True
 
 
+def tuned_decoder(code, pcm, code_name: str, rows: int, n_branches=9, mode=None, alpha=0.75, max_iter=8,
+                  precision=0, flags=0):
+    """A decoder with the cached layout (packed or not) and grid; the
+    defaults when nothing is cached."""
+    from . import binding as B
+    mode = B.MODE_RESTART if mode is None else mode
+    entry = load().get(key(code_name, rows, precision, n_branches, _gpu_name()))
+    if entry and entry.get("packed16"):
+        flags |= B.PACKED16
+    dec = B.Decoder(code, pcm, n_branches=n_branches, mode=mode, alpha=alpha, max_iter=max_iter,
+                    precision=precision, flags=flags)
+    if entry and dec.specialized:
+        dec.set_tuning(entry["waves_per_cu"])
+    return dec
+
+
 def default_frames(N: int) -> int:
-    """Batch size of the tuning runs: the frames of one Eb/N0 point of the sweep
-    (N = 63) and of the 127-bit workloads.  The best grid depends on it: a smaller batch
+    """Batch size of the tuning runs: the benchmark's decode call of the sweep
+    (11 Eb/N0 points of 10^6 frames, N = 63), and one 4 10^6-frame point of
+    the 127-bit workloads.  The best choice depends on it: a smaller batch
     favours fewer resident frames, whose drain at the end of the launch is
-    shorter."""
-    return 1_000_000 if N <= 64 else 4_000_000
+    shorter (the packed kernels, 128 frames per wave, lose at 10^6 frames and
+    win at 11 10^6)."""
+    return 11_000_000 if N <= 64 else 4_000_000
 
 
-def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 0, reps: int = 3,
-         seed: int = 99, write: bool = True):
-    """Time every candidate and return the best (also cached when write)."""
-    import numpy as np
+def _batch(code_name, N, frames, ebn0, seed, block_frames=500_000):
+    """Synthetic frames of one code on the device (generated in blocks)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import torch
 
     import synth
+    ld = 64 if N <= 64 else 128
+    llr = torch.empty((frames, ld), dtype=torch.float32, device="cuda")
+    d_o = torch.empty(frames, dtype=torch.uint8, device="cuda")
+    starts = list(range(0, frames, block_frames))
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 4)) as ex:
+        parts = ex.map(lambda k: synth.frames(code_name, min(block_frames, frames - starts[k]), ebn0, seed=seed,
+                                              block=k), range(len(starts)))
+        for f0, q in zip(starts, parts):
+            llr[f0:f0 + len(q.d_o)].copy_(torch.from_numpy(q.llr))
+            d_o[f0:f0 + len(q.d_o)].copy_(torch.from_numpy(q.d_o))
+    return llr, d_o
+
+
+def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 0, reps: int = 3,
+         seed: int = 99, write: bool = True, batch=None):
+    """Time every grid of one decoder and return the best (also cached when
+    write).  batch: (llr FP32 [F][ld], d_o [F]) on the device, else generated."""
+    import torch
+
     from . import binding as B
-    frames = frames or default_frames(decoder.N)
-    fr = synth.frames(code_name, frames, ebn0, seed=seed)
-    llr = torch.from_numpy(fr.llr).cuda()
+    if batch is None:
+        batch = _batch(code_name, decoder.N, frames or default_frames(decoder.N), ebn0, seed)
+    llr, d_o = batch
     if decoder.precision == B.FIX8:
         q = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
         B.quantize_llr(llr, decoder.N, 4.0, q)
         llr = q
-    d_o = torch.from_numpy(fr.d_o).cuda()
-    F = frames
+    F = llr.shape[0]
     bits = torch.empty((F, decoder.W64), dtype=torch.int64, device="cuda")
     it = torch.empty(F, dtype=torch.uint8, device="cuda")
     fl = torch.empty(F, dtype=torch.uint8, device="cuda")
@@ -95,13 +139,42 @@ def tune(decoder, code_name: str, rows: int, ebn0: float = 3.0, frames: int = 0,
     dt, wv = results[0]
     decoder.set_tuning(wv)
     best = {"waves_per_cu": wv, "frames_per_s": F / dt, "ebn0": ebn0, "frames": F,
-            "default_frames_per_s": F / next(d for d, w in results if w == 0)}
+            "default_frames_per_s": F / next(d for d, w in results if w == 0),
+            "packed16": bool(decoder.flags & B.PACKED16)}
     if write:
         cache = load()
         cache[key(code_name, rows, decoder.precision, decoder.n_branches, _gpu_name())] = best
         with open(CACHE, "w") as fh:
             json.dump(cache, fh, indent=1, sort_keys=True)
     return best, results
+
+
+def tune_layout(code, pcm, code_name: str, rows: int, precision: int, ebn0: float = 3.0, frames: int = 0,
+                reps: int = 3, seed: int = 99, write: bool = True):
+    """Time every layout (fixed point: 64 or 128 frames per wave) and grid of
+    a nine-branch decoder; cache and return the best entry and every layout's
+    (best entry, timings)."""
+    from . import binding as B
+    cands = [0] + ([B.PACKED16] if precision == B.FIX8 else [])
+    batch = None
+    out = []
+    for fl in cands:
+        dec = B.Decoder(code, pcm, n_branches=9, max_iter=8, precision=precision, flags=fl)
+        if not dec.specialized:
+            continue
+        if batch is None:
+            batch = _batch(code_name, code.N, frames or default_frames(code.N), ebn0, seed)
+        out.append(tune(dec, code_name, rows, ebn0=ebn0, reps=reps, seed=seed, write=False, batch=batch))
+    if not out:
+        return None, out
+    best = dict(max((b for b, _ in out), key=lambda b: b["frames_per_s"]))
+    best["default_frames_per_s"] = out[0][0]["default_frames_per_s"]  # the 64-frame layout, default grid
+    if write:
+        cache = load()
+        cache[key(code_name, rows, precision, 9, _gpu_name())] = best
+        with open(CACHE, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+    return best, out
 
 
 def main():
@@ -111,7 +184,8 @@ def main():
     ap.add_argument("--codes", default="bch127_64:72,bch127_99:33,bch63_36:122,bch63_45:33")
     ap.add_argument("--precisions", default="fp32,fix8")
     ap.add_argument("--ebn0", type=float, default=3.0)
-    ap.add_argument("--frames", type=int, default=0, help="frames per timed launch (0: 10^6 for N = 63, 4 10^6 for N = 127)")
+    ap.add_argument("--frames", type=int, default=0,
+                    help="frames per timed launch (0: 11 10^6 for N = 63, 4 10^6 for N = 127)")
     ap.add_argument("--out", default=CACHE, help="JSON cache to update")
     args = ap.parse_args()
     CACHE = args.out
@@ -123,14 +197,14 @@ def main():
         code = B.Code(d.m, d.prim, d.t)
         pcm = B.Pcm.build(code, target_rows=rows, seed=1)
         for prec in args.precisions.split(","):
-            dec = B.Decoder(code, pcm, n_branches=9, max_iter=8, precision=B.FIX8 if prec == "fix8" else B.FP32)
-            if not dec.specialized:
+            best, res = tune_layout(code, pcm, name, rows, B.FIX8 if prec == "fix8" else B.FP32,
+                                    ebn0=args.ebn0, frames=args.frames)
+            if best is None:
                 print("%s/%d/%s: no specialised kernel, skipped" % (name, rows, prec), flush=True)
                 continue
-            best, res = tune(dec, name, rows, ebn0=args.ebn0, frames=args.frames)
-            print("%s/%d/%s: best waves %d: %.1fM frames/s (default %.1fM)" % (
-                name, rows, prec, best["waves_per_cu"], best["frames_per_s"] / 1e6,
-                best["default_frames_per_s"] / 1e6), flush=True)
+            print("%s/%d/%s: best %s, waves %d: %.1fM frames/s (default %.1fM)" % (
+                name, rows, prec, "128 frames per wave (packed)" if best["packed16"] else "64 frames per wave",
+                best["waves_per_cu"], best["frames_per_s"] / 1e6, best["default_frames_per_s"] / 1e6), flush=True)
 
 
 if __name__ == "__main__":

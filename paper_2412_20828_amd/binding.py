@@ -204,7 +204,7 @@ class Decoder:
         _check(lib().bch_decoder_create(code.h, pcm.h, ctypes.byref(p), ctypes.byref(h)), "bch_decoder_create")
         self.h, self.code, self.pcm = h, code, pcm
         self.N, self.n_branches, self.mode, self.alpha = code.N, n_branches, mode, alpha
-        self.max_iter, self.precision = max_iter, precision
+        self.max_iter, self.precision, self.flags = max_iter, precision, flags
         self.W64 = (code.N + 63) // 64
 
     @property
