@@ -18,10 +18,13 @@
 // first uses r quantised to 16 bits (q_u = round(r_u 2^s), s per frame), an
 // integer weighted popcount over bit-planes of q that the wave builds with
 // ballots; each candidate's quantised cost is within 63.5 units of 2^s times
-// its exact cost.  The second pass recomputes the exact FP64 cost of every
-// candidate whose quantised cost is within 128 units of the smallest, which
-// includes every candidate of least exact cost, and the wave picks the least
-// exact cost, then the first candidate.  The result is therefore the host's.
+// its exact cost; for up to KEEP_MAX candidates it is kept in LDS (one word
+// per candidate, written and read by the same lane), else the second pass
+// recomputes it.  The second pass computes the exact FP64 cost of every
+// candidate whose quantised cost is within 128 units of the smallest,
+// which includes every candidate of least exact cost, and the wave picks the
+// least exact cost, then the first candidate.  The result is therefore the
+// host's.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -82,8 +85,21 @@ __device__ __forceinline__ void next_rows(int key, int K, int &k1, int &k2)
     }
 }
 
+// pass-1 costs kept in LDS up to this many candidates (9 KB; every order-2
+// search with K <= 67).  Larger searches recompute them: 20 KB or more of LDS
+// per one-wave workgroup would cut the resident waves per CU, and measured
+// slower for K = 99.
+constexpr int KEEP_MAX = 2304;
+
+// candidates of an order-p search over K basis rows (p = 0, 1 or 2)
+__host__ __device__ inline int n_candidates(int order, int K)
+{
+    return order <= 0 ? 1 : (order == 1 ? 1 + K : 1 + K + K * (K - 1) / 2);
+}
+
 __global__ void __launch_bounds__(WAVE) osd_kernel(OsdArgs A)
 {
+    extern __shared__ uint32_t qv[];  // [n_candidates] quantised costs of pass 1
     __shared__ float r[128];
     __shared__ uint32_t rowl[128][4];  // working generator rows after elimination
     __shared__ int mrb[128];
@@ -221,7 +237,7 @@ __global__ void __launch_bounds__(WAVE) osd_kernel(OsdArgs A)
             }
             return t;
         };
-        const int nk = A.order <= 0 ? 1 : (A.order == 1 ? 1 + K : 1 + K + K * (K - 1) / 2);
+        const int nk = n_candidates(A.order, K);
         // pass 1: least quantised cost
         uint32_t qmin = 0xffffffffu;
         {
@@ -234,6 +250,8 @@ __global__ void __launch_bounds__(WAVE) osd_kernel(OsdArgs A)
                 for (int w = 0; w < 4; w++)
                     x[w] = d0[w] ^ (k1 >= 0 ? rowl[k1][w] : 0u) ^ (k2 >= 0 ? rowl[k2][w] : 0u);
                 const uint32_t qc = qcost(x);
+                if (A.keep_costs)
+                    qv[key] = qc;
                 qmin = qc < qmin ? qc : qmin;
                 if (key + WAVE < nk)
                     next_rows(key + WAVE, K, k1, k2);
@@ -253,10 +271,21 @@ __global__ void __launch_bounds__(WAVE) osd_kernel(OsdArgs A)
                 key_rows(lane, K, k1, k2);
             for (int key = lane; key < nk; key += WAVE) {
                 uint32_t x[4];
+                bool near;
+                if (A.keep_costs) {
+                    near = qv[key] <= thr;
+                } else {
 #pragma unroll
-                for (int w = 0; w < 4; w++)
-                    x[w] = d0[w] ^ (k1 >= 0 ? rowl[k1][w] : 0u) ^ (k2 >= 0 ? rowl[k2][w] : 0u);
-                if (qcost(x) <= thr) {
+                    for (int w = 0; w < 4; w++)
+                        x[w] = d0[w] ^ (k1 >= 0 ? rowl[k1][w] : 0u) ^ (k2 >= 0 ? rowl[k2][w] : 0u);
+                    near = qcost(x) <= thr;
+                }
+                if (near) {
+                    if (A.keep_costs) {
+#pragma unroll
+                        for (int w = 0; w < 4; w++)
+                            x[w] = d0[w] ^ (k1 >= 0 ? rowl[k1][w] : 0u) ^ (k2 >= 0 ? rowl[k2][w] : 0u);
+                    }
                     double d = 0.0;
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
@@ -301,8 +330,9 @@ __global__ void __launch_bounds__(WAVE) osd_kernel(OsdArgs A)
 
 }  // namespace
 
-hipError_t launch_osd(const OsdArgs &A, int n_cu, hipStream_t stream)
+hipError_t launch_osd(const OsdArgs &args, int n_cu, hipStream_t stream)
 {
+    OsdArgs A = args;
     if (A.N > 128 || A.K > 128 || A.K < 1)
         return hipErrorInvalidValue;
     int64_t grid = (int64_t)n_cu * 16;
@@ -310,7 +340,10 @@ hipError_t launch_osd(const OsdArgs &A, int n_cu, hipStream_t stream)
         grid = A.F;
     if (grid < 1)
         return hipSuccess;
-    hipLaunchKernelGGL(osd_kernel, dim3((unsigned)grid), dim3(WAVE), 0, stream, A);
+    const int nk = n_candidates(A.order, A.K);
+    A.keep_costs = nk <= KEEP_MAX ? 1 : 0;
+    const size_t lds = A.keep_costs ? sizeof(uint32_t) * (size_t)nk : 0;
+    hipLaunchKernelGGL(osd_kernel, dim3((unsigned)grid), dim3(WAVE), lds, stream, A);
     return hipGetLastError();
 }
 

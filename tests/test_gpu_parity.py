@@ -183,7 +183,8 @@ def test_full_size_batches_sampled(B, name, rows, F, ebn0):
     ("bch63_36", 122, 1_000_000, (1.0, 6.0, 0.5), "fp32"),
     ("bch127_64", 72, 4_000_000, (2.0, 5.0, 0.5), "fp32"),
     ("bch127_64", 72, 4_000_000, (2.0, 5.0, 0.5), "fix8"),
-    ("bch127_64", 72, 4_000_000, (2.0, 5.0, 0.5), "fix8_packed16")])
+    ("bch127_64", 72, 4_000_000, (2.0, 5.0, 0.5), "fix8_packed16"),
+    ("bch63_36", 122, 1_000_000, (1.0, 6.0, 0.5), "fix8_packed16")])
 def test_sweep_in_one_call_sampled(B, name, rows, per, grid, precision):
     """A whole Eb/N0 sweep of one code in a single decode call, as the
     benchmark launches it by default: 11 x 1,000,000 frames for length 63 and
