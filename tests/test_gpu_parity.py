@@ -299,6 +299,26 @@ def test_edge_cases(B):
         assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])
 
 
+@pytest.mark.parametrize("prec,flags", [("fp32", "SMALL_ALWAYS"), ("fp32", "SMALL_NEVER"), ("fix8", "SMALL_ALWAYS"),
+                                         ("fix8", "PACKED16")])
+def test_edge_cases_127(B, prec, flags):
+    """Empty, single-frame and all-zero batches on each N = 127 kernel."""
+    c, p = lib_objects(B, "bch127_64", 72)
+    precision = B.FIX8 if prec == "fix8" else B.FP32
+    dec = B.Decoder(c, p, n_branches=9, max_iter=8, precision=precision, flags=getattr(B, flags))
+    assert dec.specialized
+    dt = torch.int8 if prec == "fix8" else torch.float32
+    bits, its, flg, _ = dec.decode(torch.empty((0, 128), dtype=dt, device="cuda"),
+                                   torch.empty(0, dtype=torch.uint8, device="cuda"))
+    assert bits.shape[0] == 0
+    for F in (1, 129):
+        z = torch.zeros((F, 128), dtype=dt, device="cuda")
+        d_o = torch.arange(F, dtype=torch.int32, device="cuda").remainder(42).to(torch.uint8)
+        bits, its, flg, _ = dec.decode(z, d_o)
+        torch.cuda.synchronize()
+        assert (bits.cpu() == 0).all() and (its.cpu() == 1).all() and (flg.cpu() == 1).all()
+
+
 def test_syndrome_kernel(B):
     c, _ = lib_objects(B, "bch127_99", 33)
     fr = synth.frames("bch127_99", 300, 4.0, seed=3)
