@@ -18,9 +18,10 @@
 // first uses r quantised to 16 bits (q_u = round(r_u 2^s), s per frame), an
 // integer weighted popcount over bit-planes of q that the wave builds with
 // ballots; each candidate's quantised cost is within 63.5 units of 2^s times
-// its exact cost; for up to KEEP_MAX candidates it is kept in LDS (one word
-// per candidate, written and read by the same lane), else the second pass
-// recomputes it.  The second pass computes the exact FP64 cost of every
+// its exact cost, and it is kept in LDS (written and read by the same lane):
+// as a word for up to KEEP_MAX candidates, else as a half-word saturated at
+// 65535, which the second pass recomputes only when the threshold below
+// reaches 65535.  The second pass computes the exact FP64 cost of every
 // candidate whose quantised cost is within 128 units of the smallest,
 // which includes every candidate of least exact cost, and the wave picks the
 // least exact cost, then the first candidate.  The result is therefore the
@@ -85,10 +86,10 @@ __device__ __forceinline__ void next_rows(int key, int K, int &k1, int &k2)
     }
 }
 
-// pass-1 costs kept in LDS up to this many candidates (9 KB; every order-2
-// search with K <= 67).  Larger searches recompute them: 20 KB or more of LDS
-// per one-wave workgroup would cut the resident waves per CU, and measured
-// slower for K = 99.
+// pass-1 costs kept in LDS as words up to this many candidates (9 KB; every
+// order-2 search with K <= 67); larger searches keep saturated half-words
+// (at most 16.5 KB for K = 128): a word each, 20 KB for K = 99, cut the
+// resident waves per CU and measured slower than recomputing.
 constexpr int KEEP_MAX = 2304;
 
 // candidates of an order-p search over K basis rows (p = 0, 1 or 2)
@@ -250,8 +251,10 @@ __global__ void __launch_bounds__(WAVE) osd_kernel(OsdArgs A)
                 for (int w = 0; w < 4; w++)
                     x[w] = d0[w] ^ (k1 >= 0 ? rowl[k1][w] : 0u) ^ (k2 >= 0 ? rowl[k2][w] : 0u);
                 const uint32_t qc = qcost(x);
-                if (A.keep_costs)
+                if (A.keep_costs == 1)
                     qv[key] = qc;
+                else
+                    reinterpret_cast<uint16_t *>(qv)[key] = (uint16_t)(qc < 65535u ? qc : 65535u);
                 qmin = qc < qmin ? qc : qmin;
                 if (key + WAVE < nk)
                     next_rows(key + WAVE, K, k1, k2);
@@ -270,22 +273,19 @@ __global__ void __launch_bounds__(WAVE) osd_kernel(OsdArgs A)
             if (lane < nk)
                 key_rows(lane, K, k1, k2);
             for (int key = lane; key < nk; key += WAVE) {
+                // the stored cost, or 65535 for "at least 65535"
+                const uint32_t st = A.keep_costs == 1 ? qv[key] : reinterpret_cast<const uint16_t *>(qv)[key];
+                const bool sat = A.keep_costs != 1 && st == 65535u;
+                bool near = sat ? thr >= 65535u : st <= thr;
                 uint32_t x[4];
-                bool near;
-                if (A.keep_costs) {
-                    near = qv[key] <= thr;
-                } else {
+                if (near) {
 #pragma unroll
                     for (int w = 0; w < 4; w++)
                         x[w] = d0[w] ^ (k1 >= 0 ? rowl[k1][w] : 0u) ^ (k2 >= 0 ? rowl[k2][w] : 0u);
-                    near = qcost(x) <= thr;
+                    if (sat)
+                        near = qcost(x) <= thr;
                 }
                 if (near) {
-                    if (A.keep_costs) {
-#pragma unroll
-                        for (int w = 0; w < 4; w++)
-                            x[w] = d0[w] ^ (k1 >= 0 ? rowl[k1][w] : 0u) ^ (k2 >= 0 ? rowl[k2][w] : 0u);
-                    }
                     double d = 0.0;
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
@@ -341,8 +341,8 @@ hipError_t launch_osd(const OsdArgs &args, int n_cu, hipStream_t stream)
     if (grid < 1)
         return hipSuccess;
     const int nk = n_candidates(A.order, A.K);
-    A.keep_costs = nk <= KEEP_MAX ? 1 : 0;
-    const size_t lds = A.keep_costs ? sizeof(uint32_t) * (size_t)nk : 0;
+    A.keep_costs = nk <= KEEP_MAX ? 1 : 2;
+    const size_t lds = (A.keep_costs == 1 ? sizeof(uint32_t) : sizeof(uint16_t)) * (size_t)nk;
     hipLaunchKernelGGL(osd_kernel, dim3((unsigned)grid), dim3(WAVE), lds, stream, A);
     return hipGetLastError();
 }

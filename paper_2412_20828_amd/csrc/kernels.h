@@ -47,7 +47,7 @@ struct OsdArgs {
     int64_t bits_ld;
     const uint32_t *G;    // [K][4] generator rows, bit i of row k = word i / 32, bit i % 32
     int N, K, order;
-    int keep_costs;       // set by launch_osd: pass-1 costs kept in LDS
+    int keep_costs;       // set by launch_osd: pass-1 costs in LDS as words (1) or saturated half-words (2)
 };
 
 hipError_t launch_osd(const OsdArgs &a, int n_cu, hipStream_t stream);

@@ -623,15 +623,21 @@ def test_mixed_batch_graph_replay(B):
 @pytest.mark.parametrize("name", ["bch63_36", "bch63_45", "bch127_64", "bch127_78", "bch127_99"])
 def test_device_osd_matches_oracle(B, name):
     """Device OSD-p (p = 0, 1, 2) equals the oracle's OSD bit for bit, on
-    noisy frames and on integer-valued LLRs (equal reliabilities: ties in the
-    ordering and in the candidate costs)."""
+    noisy frames, on integer-valued LLRs (equal reliabilities: ties in the
+    ordering and in the candidate costs), and on frames of equal magnitudes
+    with random signs and at -3 dB, whose least candidate costs exceed the
+    16-bit range the device keeps for large searches."""
     c, p = lib_objects(B, name, 0)
     dec = B.Decoder(c, p, n_branches=1, mode=B.MODE_EXTRINSIC, max_iter=4)
     oc = oracle_code(name)
     fr = synth.frames(name, 200, 1.5, seed=61)
     tied = np.round(fr.llr[:100] / 3.0).astype(np.float32)  # many |L| equal
     tied[:, oc.N:] = 0.0
-    llr_h = np.concatenate([fr.llr, tied])
+    rng = np.random.default_rng(64)
+    flat = np.zeros_like(fr.llr[:40])
+    flat[:, :oc.N] = np.where(rng.random((40, oc.N)) < 0.5, -2.5, 2.5)
+    deep = synth.frames(name, 40, -3.0, seed=65).llr
+    llr_h = np.concatenate([fr.llr, tied, flat, deep])
     llr_h[5] = 0.0  # all-zero frame: every candidate costs 0
     llr = torch.from_numpy(llr_h).cuda()
     for order in (0, 1, 2):
