@@ -42,6 +42,7 @@ import synth  # noqa: E402
 # lanes x 2.4 GHz, the published FP32 vector rate of 157.3 TFLOP/s with an FMA
 # counted as one lane-operation (two FLOPs)
 VALU_PEAK_OPS = 256 * 128 * 2.4e9
+HBM_PEAK_BYTES = 8.0e12  # published HBM3E bandwidth of one MI355X
 WORKLOADS = {
     # name: (codes with H_o rows, Eb/N0 grid, frames per point, precisions, description)
     "sweep63": ([("bch63_45", 33), ("bch63_36", 122)], "1.0:6.0:0.5", 1_000_000, ["fp32"],
@@ -759,6 +760,8 @@ def main():
                      "kernel": dom, "launches_per_step": n_dom, "avg_launch_ms": t_dom / n_dom * 1e3,
                      "algorithmic_ops_per_launch": ops_dom / n_dom,
                      "traffic_bytes_per_frame": (list(TRAFFIC_B_PER_FRAME[dom]) if traffic else None),
+                     "hbm": ({"achieved_gb_s": traffic / (t_dom / n_dom) / 1e9, "peak_gb_s": HBM_PEAK_BYTES / 1e9,
+                              "frac": traffic / (t_dom / n_dom) / HBM_PEAK_BYTES} if traffic else None),
                      "all_kernels": {"achieved": achieved_all / 1e12, "frac": achieved_all / VALU_PEAK_OPS}},
         "points": per_point,
         "input_generation_s": gen_s,
