@@ -121,6 +121,15 @@ _MED3U = """__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, ui
 """
 
 
+def _parity(S, masks):
+    """Expression whose bit 0 is the parity of the sign bits S & masks: the
+    masked words are folded with XOR first (the parity of an XOR is the XOR
+    of the parities), so a row costs one popcount however many words N
+    takes."""
+    terms = ["(%s[%d] & 0x%08xu)" % (S, k, m) for k, m in enumerate(masks) if m]
+    return "__builtin_popcount(%s)" % " ^ ".join(terms)
+
+
 def _forward(cols):
     """Lines of a row's min1 <= min2 chain over A[cols] in integer form,
     ending with float m1, m2."""
@@ -155,7 +164,7 @@ def body_source_ilp(H: np.ndarray, fix8: bool = False, group: int = 2) -> str:
             masks = [0] * W32
             for c in cs:
                 masks[c // 32] |= 1 << (c % 32)
-            cnt = " + ".join("__builtin_popcount(S[%d] & 0x%08xu)" % (k, masks[k]) for k in range(W32) if masks[k])
+            cnt = _parity("S", masks)
             out.append("        const float sg%d = __uint_as_float(0x3f800000u | ((%s) << 31));" % (r, cnt))
             c0, c1 = cs[0], cs[1]
             out.append("        uint32_t u1_%d = min(__float_as_uint(A[%d]), __float_as_uint(A[%d])), "
@@ -208,7 +217,7 @@ def body_source(H: np.ndarray, accumulate: bool = False) -> str:
         masks = [0] * W32
         for c in cols:
             masks[c // 32] |= 1 << (c % 32)
-        cnt = " + ".join("__builtin_popcount(S[%d] & 0x%08xu)" % (k, masks[k]) for k in range(W32) if masks[k])
+        cnt = _parity("S", masks)
         out.append("    { // row %d" % j)
         out.append("        const uint32_t cnt = %s;" % cnt)
         out.append("        const float sg = __uint_as_float(0x3f800000u | (cnt << 31));")
@@ -247,7 +256,7 @@ def body_source_fix8(H: np.ndarray, accumulate: bool = False) -> str:
         masks = [0] * W32
         for c in cols:
             masks[c // 32] |= 1 << (c % 32)
-        cnt = " + ".join("__builtin_popcount(S[%d] & 0x%08xu)" % (k, masks[k]) for k in range(W32) if masks[k])
+        cnt = _parity("S", masks)
         out.append("    { // row %d" % j)
         out.append("        const uint32_t cnt = %s;" % cnt)
         out.append("        const float sg = __uint_as_float(0x3f800000u | (cnt << 31));")
@@ -288,8 +297,7 @@ def body_source_pk16(H: np.ndarray, B: int) -> str:
         masks = [0] * W32
         for c in cols:
             masks[c // 32] |= 1 << (c % 32)
-        cl = " + ".join("__builtin_popcount(SL[%d] & 0x%08xu)" % (k, masks[k]) for k in range(W32) if masks[k])
-        ch = " + ".join("__builtin_popcount(SH[%d] & 0x%08xu)" % (k, masks[k]) for k in range(W32) if masks[k])
+        cl, ch = _parity("SL", masks), _parity("SH", masks)
         out.append("    { // row %d" % j)
         out.append("        const uint32_t cl = %s, ch = %s;" % (cl, ch))
         out.append("        const v2s sg = __builtin_bit_cast(v2s, ((cl & 1u) ? 0xffffu : 1u) | "
