@@ -121,6 +121,17 @@ _MED3U = """__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, ui
 """
 
 
+def _sign_masks(cols, N):
+    """Row masks over the sign words S of the 32-bit kernels, which shift the
+    sign bits in coordinate by coordinate ((S << 1) | sign): coordinate c of
+    word w = c // 32 sits at bit min(N, 32 (w + 1)) - 1 - c."""
+    masks = [0] * ((N + 31) // 32)
+    for c in cols:
+        w = c // 32
+        masks[w] |= 1 << (min(N, 32 * (w + 1)) - 1 - c)
+    return masks
+
+
 def _parity(S, masks):
     """Expression whose bit 0 is the parity of the sign bits S & masks: the
     masked words are folded with XOR first (the parity of an XOR is the XOR
@@ -151,7 +162,6 @@ def body_source_ilp(H: np.ndarray, fix8: bool = False, group: int = 2) -> str:
     pinned by scheduling barriers.  Every column is still updated by its rows
     in ascending order."""
     M, N = H.shape
-    W32 = (N + 31) // 32
     out = [_MED3U, "__device__ __forceinline__ void body(const float *__restrict__ A, "
            "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
     for j0 in range(0, M, group):
@@ -161,10 +171,7 @@ def body_source_ilp(H: np.ndarray, fix8: bool = False, group: int = 2) -> str:
         for r, j in enumerate(rows):
             cs = [int(c) for c in np.nonzero(H[j])[0]]
             cols[r] = cs
-            masks = [0] * W32
-            for c in cs:
-                masks[c // 32] |= 1 << (c % 32)
-            cnt = _parity("S", masks)
+            cnt = _parity("S", _sign_masks(cs, N))
             out.append("        const float sg%d = __uint_as_float(0x3f800000u | ((%s) << 31));" % (r, cnt))
             c0, c1 = cs[0], cs[1]
             out.append("        uint32_t u1_%d = min(__float_as_uint(A[%d]), __float_as_uint(A[%d])), "
@@ -208,16 +215,12 @@ def body_source(H: np.ndarray, accumulate: bool = False) -> str:
     """Row function of the FP32 decoder.  accumulate: add every edge's c2v into
     T (T holds a running sum over branches) instead of overwriting T."""
     M, N = H.shape
-    W32 = (N + 31) // 32
     out = [_MED3U, "__device__ __forceinline__ void body(const float *__restrict__ A, "
            "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
     touched = [False] * N
     for j in range(M):
         cols = [int(c) for c in np.nonzero(H[j])[0]]
-        masks = [0] * W32
-        for c in cols:
-            masks[c // 32] |= 1 << (c % 32)
-        cnt = _parity("S", masks)
+        cnt = _parity("S", _sign_masks(cols, N))
         out.append("    { // row %d" % j)
         out.append("        const uint32_t cnt = %s;" % cnt)
         out.append("        const float sg = __uint_as_float(0x3f800000u | (cnt << 31));")
@@ -247,16 +250,12 @@ def body_source_fix8(H: np.ndarray, accumulate: bool = False) -> str:
     (A >= min1 + 1 gives a third argument below 0).  All values are small
     integers, so every step is exact."""
     M, N = H.shape
-    W32 = (N + 31) // 32
     out = [_MED3U, "__device__ __forceinline__ void body(const float *__restrict__ A, "
            "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
     touched = [False] * N
     for j in range(M):
         cols = [int(c) for c in np.nonzero(H[j])[0]]
-        masks = [0] * W32
-        for c in cols:
-            masks[c // 32] |= 1 << (c % 32)
-        cnt = _parity("S", masks)
+        cnt = _parity("S", _sign_masks(cols, N))
         out.append("    { // row %d" % j)
         out.append("        const uint32_t cnt = %s;" % cnt)
         out.append("        const float sg = __uint_as_float(0x3f800000u | (cnt << 31));")
