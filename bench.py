@@ -67,13 +67,13 @@ FIX_SCALE = 4.0
 # WRITE_SIZE runs of the default sweep (one call of 11,000,000 frames per code),
 # each scaled by what the same counter reads for a plain 1 GiB device copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  It holds only for the kernel sources the counters were taken on
-# (hash of the grouped kernel template and its rotation helpers, the launch
-# header and the row-function generator); any other build reports traffic
-# null.
-TRAFFIC_SRC_HASH = "efc7049ea5a6103e"
+# (hash of the grouped kernel template, its rotation and frame hand-out
+# helpers, the launch header and the row-function generator); any other build
+# reports traffic null.
+TRAFFIC_SRC_HASH = "ad8f123bafebf13c"
 TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written) bytes per frame
-    "spec_bch63_36_m122_b9": (301.81, 73.42),
-    "spec_bch63_45_m33_b9": (267.26, 69.33),
+    "spec_bch63_36_m122_b9": (300.21, 73.55),
+    "spec_bch63_45_m33_b9": (265.20, 68.51),
 }
 
 
@@ -81,7 +81,8 @@ def kernel_src_hash():
     import hashlib
     pkg = os.path.join(ROOT, "paper_2412_20828_amd")
     outer = hashlib.sha256()
-    for f in ("csrc/nms_spec_group.inc", "csrc/nms_spec_rot.inc", "csrc/spec_launch.h", "gen_spec.py"):
+    for f in ("csrc/nms_spec_group.inc", "csrc/nms_spec_rot.inc", "csrc/nms_spec_cursor.inc", "csrc/spec_launch.h",
+              "gen_spec.py"):
         with open(os.path.join(pkg, f), "rb") as fh:
             outer.update(hashlib.sha256(fh.read()).digest())
     return outer.hexdigest()[:16]
