@@ -16,7 +16,9 @@ Other workloads (--workload): "fix127", BCH(127,64) and BCH(127,99) at
 2.0..5.0 dB, 4,000,000 frames per point, FP32 and int8 fixed point; "mixed",
 16,000,000 frames of BCH(127,64)/(127,99)/(63,36) interleaved per frame
 (50/25/25 %) at Eb/N0 drawn per frame from U[1.5, 5] dB, decoded in one
-mixed-code call, FP32 and int8.
+mixed-code call, FP32 and int8; "serve", the continuous-batching service
+with OSD-2; "latency", decode-call latency against the call size; "alpha",
+"ablation" and "beta", experiments of the method.
 
 Prints one JSON line with frames/s (value), information Gbit/s, per-launch
 p50/p99 latency, the VALU roofline of the decode kernel and the CPU oracle
@@ -56,6 +58,7 @@ WORKLOADS = {
     "alpha": (None, "", 0, ["fp32"], "alpha sweep"),
     "ablation": (None, "", 0, ["fp32"], "branch-count ablation"),
     "beta": (None, "", 0, ["fp32"], "H_o redundancy sweep"),
+    "latency": (None, "", 0, ["fp32"], "decode-call latency"),
     "mixed": ([("bch127_64", 72), ("bch127_99", 33), ("bch63_36", 122)], "1.5:5.0", 16_000_000, ["fp32", "fix8"],
               "mixed-code batch, per frame 50% BCH(127,64) H_o 72x127, 25% BCH(127,99) H_o 33x127, "
               "25% BCH(63,36) H_o 122x63 in one call, enhanced NMS 9 branches, restart mode, max 8 iterations, "
@@ -413,6 +416,55 @@ def timed_decode(dec, llr, d_o, torch, reps=2):
     return bits.cpu().numpy().view(np.uint64), it.cpu().numpy(), fl.cpu().numpy(), a.elapsed_time(b) / 1e3 / reps
 
 
+def run_latency(args):
+    """Latency of one decode call against its size: each of the four workload
+    codes (9 branches, restart mode, FP32, I_m = 8) at 3 dB, F in {64, 1024,
+    16384, 65536} frames per call (the service's batch sizes), 50 timed calls
+    after 5 warm-up calls, each timed with events on the decode stream
+    (bucketing prepass included).  A call ends when its slowest frame stops,
+    so the latency is that of up to 8 iterations; the row names the kernel the
+    library picked for the size."""
+    import torch
+
+    from paper_2412_20828_amd import binding as B
+    stream = torch.cuda.current_stream()
+    rows = []
+    for ci, (name, rows_h) in enumerate(SERVE_CODES):
+        d = B.CODE_DEFS[name]
+        code = B.Code(d.m, d.prim, d.t)
+        pcm = B.Pcm.build(code, target_rows=rows_h, seed=1)
+        dec = B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8)
+        fr = synth.frames(name, 65536, 3.0, seed=7000 + ci)
+        llr_all, d_o_all = torch.from_numpy(fr.llr).cuda(), torch.from_numpy(fr.d_o).cuda()
+        for F in (64, 1024, 16384, 65536):
+            llr, d_o = llr_all[:F].contiguous(), d_o_all[:F].contiguous()
+            bits = torch.empty((F, dec.W64), dtype=torch.int64, device="cuda")
+            it = torch.empty(F, dtype=torch.uint8, device="cuda")
+            fl = torch.empty(F, dtype=torch.uint8, device="cuda")
+            ws = torch.empty(max(1, dec.workspace_size(F)), dtype=torch.uint8, device="cuda")
+            for _ in range(5):
+                dec.decode_into(llr, d_o, bits, it, fl, workspace=ws, stream=stream)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
+            torch.cuda.synchronize()
+            for a, b in ev:
+                a.record(stream)
+                dec.decode_into(llr, d_o, bits, it, fl, workspace=ws, stream=stream)
+                b.record(stream)
+            torch.cuda.synchronize()
+            ms = np.array([a.elapsed_time(b) for a, b in ev])
+            rows.append({"code": name, "frames": F, "kernel": dec.kernel_name(F),
+                         "latency_ms_p50": float(np.percentile(ms, 50)), "latency_ms_p99": float(np.percentile(ms, 99)),
+                         "max_iters": int(it.max().item()), "frames_per_s": F / (float(np.median(ms)) / 1e3)})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    best = min(r["latency_ms_p50"] for r in rows)
+    print(json.dumps({"metric": "decoded frames/s & info Gbit/s at matched FER vs oracle; p50/p99 latency",
+                      "workload": "latency", "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
+                      "vs_baseline": None, "steps": 50, "warmup": 5, "value": best, "unit": "ms",
+                      "config": {"workload": "decode-call latency against call size, 9 branches, restart mode, FP32, "
+                                             "I_m 8, 3 dB, codes of the service, 64-65536 frames per call"},
+                      "rows": rows}))
+
+
 def run_experiment(args):
     """Experiments of the method on the GPU kernels.
 
@@ -624,6 +676,8 @@ def main():
         if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < need:
             os.environ["GPU_MAX_HW_QUEUES"] = str(need)
         return run_serve(args)
+    if args.workload == "latency":
+        return run_latency(args)
     if args.workload in ("alpha", "ablation", "beta"):
         return run_experiment(args)
 
