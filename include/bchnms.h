@@ -136,7 +136,8 @@ enum {
                                   branches of 64 frames on three waves) where registered */
     BCH_DEC_SMALL_NEVER = 8    /* N = 127: never use it.  Without either flag a decode of at
                                   most 128 frames per CU uses it, a larger one the kernel
-                                  of one wave per 64 frames; the results are the same */
+                                  of one wave per 64 frames; the results are the same.
+                                  Both flags together, or any other bit, give BCH_EINVAL */
 };
 typedef struct {
     int n_branches; /* 1, 3 or 9 */

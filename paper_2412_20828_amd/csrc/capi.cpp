@@ -356,6 +356,10 @@ int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params,
         return fail(BCH_EINVAL, "max_iter must be in [1, 64]");
     if (q.precision != BCH_FP32 && q.precision != BCH_FIX8)
         return fail(BCH_EINVAL, "unknown precision");
+    if ((q.flags & BCH_DEC_SMALL_ALWAYS) && (q.flags & BCH_DEC_SMALL_NEVER))
+        return fail(BCH_EINVAL, "BCH_DEC_SMALL_ALWAYS and BCH_DEC_SMALL_NEVER exclude each other");
+    if (q.flags & ~(BCH_DEC_FORCE_GENERIC | BCH_DEC_PACKED16 | BCH_DEC_SMALL_ALWAYS | BCH_DEC_SMALL_NEVER))
+        return fail(BCH_EINVAL, "unknown decoder flags");
     if (p.E > 65535)
         return fail(BCH_EUNSUPPORTED, "too many edges");
     auto *d = new (std::nothrow) bch_decoder_s();

@@ -81,6 +81,9 @@ def test_small_batch_kernel_selection(B):
     assert d63.kernel_name(100) == d63.kernel_name(10 ** 7) == "spec_bch63_36_m122_b9"
     gen = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8, flags=B.FORCE_GENERIC)
     assert gen.kernel_name(100) == "generic"
+    for bad in (B.SMALL_ALWAYS | B.SMALL_NEVER, 64):
+        with pytest.raises(B.BchError):
+            B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8, flags=bad)
 
 
 @pytest.mark.parametrize("flags", ["SMALL_ALWAYS", "SMALL_NEVER"])
