@@ -12,7 +12,6 @@ Usage: python -m paper_2412_20828_amd.build
 from __future__ import annotations
 
 import concurrent.futures as cf
-import hashlib
 import os
 import shutil
 import subprocess

@@ -1,7 +1,6 @@
 """The autotuner (run on an MI355X): it times the frames-per-wave layouts and
 grids of a decoder, caches the fastest, and a decoder built from the cache
 decodes every frame exactly as the default one does."""
-import numpy as np
 import pytest
 
 import synth
