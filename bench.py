@@ -331,7 +331,7 @@ def run_serve(args):
     from paper_2412_20828_amd import serving
     names = [n for n, _ in SERVE_CODES]
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    eng = serving.Engine(SERVE_CODES, slot_frames=1 << 16, n_slots=args.slots, osd_order=2, osd_on=args.osd,
+    eng = serving.Engine(SERVE_CODES, slot_frames=args.slot_frames, n_slots=args.slots, osd_order=2, osd_on=args.osd,
                          osd_threads=max(1, min(16, threads) - 2), tuned=not args.generic)
     t0 = time.time()
     tr = synth.request_trace(args.requests, 5000, len(names), 2.0, 5.0)
@@ -375,8 +375,8 @@ def run_serve(args):
         "config": {"workload": "serving: %d requests, Poisson arrivals, round(2^(12U)) frames each, code uniform "
                                "over BCH(63,36) H_o 122x63, (63,45) 33x63, (127,64) 72x127, (127,99) 33x127, "
                                "Eb/N0 U[2, 5] dB per request; enhanced NMS 9 branches, max 8 iterations on the "
-                               "GPU (%d slots of 65536 frames), OSD-2 for NMS failures %s"
-                               % (len(tr), args.slots, "on the GPU" if args.osd == "device" else
+                               "GPU (%d slots of %d frames), OSD-2 for NMS failures %s"
+                               % (len(tr), args.slots, args.slot_frames, "on the GPU" if args.osd == "device" else
                                   "on %d host threads" % max(1, min(16, threads) - 2)),
                    "mean_request_frames": mean_frames},
         "saturation": sat,
@@ -653,6 +653,7 @@ def main():
     ap.add_argument("--requests", type=int, default=3000, help="requests of the serving workload")
     ap.add_argument("--osd", default="device", choices=["device", "host"], help="serving: where OSD-2 runs")
     ap.add_argument("--slots", type=int, default=3, help="serving: batches in flight (slots)")
+    ap.add_argument("--slot-frames", type=int, default=1 << 16, help="serving: frame capacity of a slot")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
