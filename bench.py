@@ -91,12 +91,31 @@ def kernel_src_hash():
     return outer.hexdigest()[:16]
 
 
-def alg_ops_per_iteration(N, K, M, E, B):
-    """Algorithmic 32-bit operations of one iteration of one frame: per edge 8
-    (v2c 1, min1/min2/argmin 3, sign 1, c2v select and sign 2, bit-sum add 1),
+V2C_OPS = {1: 0, 2: 2, 3: 1}  # message mode -> v2c arithmetic per edge (restart, memory, extrinsic)
+
+
+def alg_ops_per_iteration(N, K, M, E, B, mode=1):
+    """Algorithmic 32-bit operations of one iteration of one frame: per edge
+    7 plus the v2c arithmetic of the message mode (none in restart mode, where
+    the v2c message is the gathered input itself; Y - own c2v in the extrinsic
+    mode; Y + other c2v sum in the memory mode, counted as S - own + Y), the 7
+    being min1/min2/argmin 3, sign 1, c2v select and sign 2, bit-sum add 1;
     per check row 2, per branch coordinate 2 (permutation and merge), plus the
     syndrome test 2 (N-K) ceil(N/64)."""
-    return 8 * B * E + 2 * B * M + 2 * B * N + 2 * (N - K) * ((N + 63) // 64)
+    per_edge = 7 + V2C_OPS[mode]
+    return per_edge * B * E + 2 * B * M + 2 * B * N + 2 * (N - K) * ((N + 63) // 64)
+
+
+# the coarse complexity account of the paper's Table 2: automorphisms per
+# iteration x iterations x rows of the parity-check matrix (x parallel
+# decoders), relative to mRRD(1) with (I1, I2, I3) = (15, 50, 1) on the
+# 18-row standard matrix of BCH(63,45)
+TABLE2_REFERENCE = (1, 15 * 50 * 1, 18)
+
+
+def table2_complexity(automorphisms, iterations, rows, parallel=1):
+    a, i, m = TABLE2_REFERENCE
+    return automorphisms * iterations * rows * parallel / (a * i * m)
 
 
 def gen_point(name, F, ebn0, seed, block_frames=125000):
@@ -341,7 +360,7 @@ def run_serve(args):
     mean_frames = float(np.mean([d.frames for d in tr]))
 
     def fresh():
-        return [serving.Request(code=d.code, llr=f.llr, d_o=f.d_o, rid=k) for k, (d, f) in enumerate(zip(tr, frs))]
+        return [serving.Request(code=d.code, llr=f.llr, rid=k) for k, (d, f) in enumerate(zip(tr, frs))]
 
     warm = fresh()[:32]
     for _ in range(args.warmup):

@@ -96,6 +96,11 @@ int bch_pcm_from_dense(bch_code code, const uint8_t *H, int M, bch_pcm *out);
  * (0 for imported / standard matrices), seed actually used. */
 int bch_pcm_info(bch_pcm pcm, int *M, int *N, int *E, int64_t *c4, int *Mr1,
                  uint64_t *seed_used);
+/* Table 1 attributes of a matrix: rows M, nonzeros E, number of length-4
+ * cycles c4 (the sum over row pairs of C(shared columns, 2)), and wstats[8] = column weight min, max, mean, population standard
+ * deviation, then the same four for the row weights.  Any output may be
+ * NULL. */
+int bch_pcm_stats(bch_pcm pcm, int *M, int *E, int64_t *c4, double wstats[8]);
 int bch_pcm_export(bch_pcm pcm, uint8_t *dense, size_t cap_bytes);
 void bch_pcm_destroy(bch_pcm pcm);
 
@@ -109,6 +114,18 @@ void bch_pcm_destroy(bch_pcm pcm);
  * d_o is the frame's random offset in [0, d_p), drawn by the caller.
  */
 int bch_make_automorphisms(int N, int n_branches, int d_o, int16_t *maps);
+
+/* The random offsets d_o of Section III-B (one per frame, uniform in
+ * [0, d_p)), drawn from a counter-based generator so that a frame's offset
+ * depends only on the key and its frame uid, never on batch position:
+ * d_o[f] = ((x >> 32) * d_p) >> 32 with x the first 64-bit word of
+ * Philox4x64-10 (Salmon et al., SC'11) at counter (frame_base + f, 0, 0, 0)
+ * under key (seed, key_hi).  d_o: F bytes, on the device (on_device = 1;
+ * enqueued on stream) or on the host (on_device = 0; written before return,
+ * stream ignored).  BCH_EINVAL for N outside [7, 127], F < 0 or
+ * frame_base < 0. */
+int bch_draw_offsets(int N, uint64_t seed, uint64_t key_hi, int64_t frame_base, int64_t F, uint8_t *d_o,
+                     int on_device, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Decoder (Algorithm 1 of Section III-B; plain NMS of Section II-A as the
@@ -165,8 +182,9 @@ void bch_decoder_destroy(bch_decoder dec);
 size_t bch_decode_workspace_size(bch_decoder dec, int64_t F);
 
 /* Decode F frames.  llr: device [F][ld] float32 (FP32) or int8 (FIX8), first N
- * entries of each row used; d_o: device [F] uint8 random offsets (ignored for
- * one branch); bits: device [F][ceil(N/64)] uint64 decoded word; iters: device
+ * entries of each row used; d_o: device [F] uint8 random offsets in [0, d_p)
+ * (bch_draw_offsets; ignored for one branch; every kernel reduces a larger
+ * value modulo d_p, which is how such a frame decodes); bits: device [F][ceil(N/64)] uint64 decoded word; iters: device
  * [F] uint8 iterations run (1..max_iter); flags: device [F] uint8, bit 0 =
  * syndrome satisfied (converged); y_trace: device [F][max_iter][ld] float32 (or
  * int32 for FIX8) per-iteration posteriors y^(t), or NULL (rows past a

@@ -68,6 +68,9 @@ def lib():
         L.orc_min_density.argtypes = [P, i32, i32, i32, P, i32]
         L.orc_build_hopt.argtypes = [P, i32, i32, i32, i32, i32, u64, i32, dbl, P, i32, P, P]
         L.orc_branch_maps.argtypes = [i32, i32, i32, P]
+        L.orc_philox4x64_10.argtypes = [P, P, P]
+        L.orc_philox4x64_10.restype = None
+        L.orc_draw_offsets.argtypes = [i32, u64, u64, ctypes.c_int64, ctypes.c_int64, P]
         for fn in (L.orc_nms_literal, L.orc_nms_fast):
             fn.argtypes = [P, i32, i32, P, i32, P, dbl, i32, i32, P, i32, P, P, P, P]
         L.orc_nms_fixed.argtypes = [P, i32, i32, P, i32, P, i32, i32, P, i32, P, P, P, P]
@@ -219,6 +222,23 @@ def branch_maps(N: int, n_branches: int, d_o: int) -> np.ndarray:
     maps = np.zeros(9 * 128, dtype=np.int16)
     _check(lib().orc_branch_maps(N, n_branches, d_o, _p(maps)), "branch_maps")
     return maps[: n_branches * N].reshape(n_branches, N).copy()
+
+
+def philox4x64_10(ctr, key):
+    """One Philox4x64-10 block: four 64-bit counter words and two key words in,
+    four output words out."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(_p(c), _p(k), _p(out))
+    return [int(v) for v in out]
+
+
+def draw_offsets(N: int, seed: int, key_hi: int, frame_base: int, F: int) -> np.ndarray:
+    """Random offsets d_o in [0, d_p) of frames frame_base .. frame_base + F - 1."""
+    d = np.zeros(F, dtype=np.uint8)
+    _check(lib().orc_draw_offsets(N, seed, key_hi, frame_base, F, _p(d)), "draw_offsets")
+    return d
 
 
 def _decode_one(fn, H, maps, L, alpha, max_iter, mode, Hsyn, trace):

@@ -39,6 +39,8 @@ int orc_build_hopt(const uint8_t *Hstd, int M, int N, int beta,
 
 /* ---- automorphisms (Section III-B) ---- */
 int orc_branch_maps(int N, int n_branches, int d_o, int16_t *maps);
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+int orc_draw_offsets(int N, uint64_t seed, uint64_t key_hi, int64_t frame_base, int64_t F, uint8_t *d_o);
 
 /* ---- decoders ---- */
 enum { ORC_R1 = 1, ORC_R2 = 2, ORC_R3 = 3 };

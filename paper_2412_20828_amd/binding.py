@@ -33,6 +33,7 @@ SYMBOLS = [
     "bch_decoder_destroy", "bch_decode_workspace_size", "bch_nms_decode_batch",
     "bch_syndrome_check", "bch_quantize_llr", "bch_osd_decode", "bch_decoder_set_tuning",
     "bch_mixed_workspace_size", "bch_mixed_decode_batch", "bch_osd_decode_device", "bch_mixed_osd_decode",
+    "bch_draw_offsets", "bch_pcm_stats",
 ]
 MAX_MIX = 8
 
@@ -81,6 +82,8 @@ def lib():
     L.bch_pcm_destroy.argtypes = [P]
     L.bch_pcm_destroy.restype = None
     L.bch_make_automorphisms.argtypes = [i32, i32, i32, P]
+    L.bch_draw_offsets.argtypes = [i32, u64, u64, i64, i64, P, i32, P]
+    L.bch_pcm_stats.argtypes = [P, P, P, P, P]
     L.bch_decoder_create.argtypes = [P, P, ctypes.POINTER(DecParams), P]
     L.bch_decoder_is_specialized.argtypes = [P]
     L.bch_decoder_kernel_name.argtypes = [P, ctypes.c_int64]
@@ -179,6 +182,16 @@ class Pcm:
         _check(lib().bch_pcm_from_dense(code.h, _np(H), H.shape[0], ctypes.byref(h)), "bch_pcm_from_dense")
         return cls(code, h)
 
+    def stats(self) -> dict:
+        """Table 1 attributes (bch_pcm_stats)."""
+        M, E, c4 = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        w = np.zeros(8, np.float64)
+        _check(lib().bch_pcm_stats(self.h, ctypes.byref(M), ctypes.byref(E), ctypes.byref(c4), _np(w)),
+               "bch_pcm_stats")
+        return {"M": M.value, "E": E.value, "c4": c4.value, "col_range": (int(w[0]), int(w[1])),
+                "col_mean": float(w[2]), "col_std": float(w[3]), "row_range": (int(w[4]), int(w[5])),
+                "row_mean": float(w[6]), "row_std": float(w[7])}
+
     def dense(self):
         out = np.zeros((self.M, self.N), np.uint8)
         _check(lib().bch_pcm_export(self.h, _np(out), out.size), "bch_pcm_export")
@@ -194,6 +207,26 @@ def make_automorphisms(N: int, n_branches: int, d_o: int):
     maps = np.zeros((n_branches, N), np.int16)
     _check(lib().bch_make_automorphisms(N, n_branches, d_o, _np(maps)), "bch_make_automorphisms")
     return maps
+
+
+def shift_period(N: int) -> int:
+    """d_p of the cyclic shifts (Section III-B): 21 for N = 63, 42 for N = 127."""
+    return {63: 21, 127: 42}.get(N, N // 3)
+
+
+def draw_offsets(N: int, seed: int, key_hi: int, frame_base: int, F: int, out=None, stream=None):
+    """Per-frame random offsets d_o in [0, d_p) (bch_draw_offsets).  out: a
+    device uint8 tensor (drawn on the device, enqueued on stream), a host
+    uint8 numpy array of F contiguous bytes, or None (a new numpy array)."""
+    if out is None or isinstance(out, np.ndarray):
+        d = np.zeros(F, np.uint8) if out is None else out
+        if d.dtype != np.uint8 or d.shape != (F,) or not d.flags.c_contiguous:
+            raise BchError("host d_o must be F contiguous uint8")
+        _check(lib().bch_draw_offsets(N, seed, key_hi, frame_base, F, _np(d), 0, None), "bch_draw_offsets")
+        return d
+    _check(lib().bch_draw_offsets(N, seed, key_hi, frame_base, F, _dptr(out), 1, _stream(stream)),
+           "bch_draw_offsets")
+    return out
 
 
 class Decoder:
@@ -249,6 +282,8 @@ class Decoder:
             ws = torch.empty(nws, dtype=torch.uint8, device=dev)
         if d_o is None:
             d_o = torch.zeros(F, dtype=torch.uint8, device=dev)
+        elif self.n_branches > 1 and F and int(d_o.max()) >= shift_period(self.N):
+            raise BchError("d_o must lie in [0, d_p) = [0, %d)" % shift_period(self.N))
         self.decode_into(llr, d_o, bits, iters, flags, tr, ws, stream)
         return bits, iters, flags, tr
 

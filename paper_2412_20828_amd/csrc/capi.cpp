@@ -1,6 +1,7 @@
 // C-ABI of the bchnms library: handle management, argument validation,
 // device tables of a decoder and the dispatch to the HIP kernels.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -10,6 +11,7 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "philox.h"
 #include "spec_registry.h"
 
 struct bch_code_s {
@@ -314,6 +316,48 @@ int bch_pcm_info(bch_pcm pcm, int *M, int *N, int *E, int64_t *c4, int *Mr1, uin
     return BCH_OK;
 }
 
+int bch_pcm_stats(bch_pcm pcm, int *M, int *E, int64_t *c4, double wstats[8])
+{
+    if (!pcm)
+        return fail(BCH_EINVAL, "pcm is NULL");
+    const Pcm &p = pcm->p;
+    if (M)
+        *M = p.M;
+    if (E)
+        *E = p.E;
+    if (c4)
+        *c4 = count_4cycles(p.rows);
+    if (wstats) {
+        // column weights, then row weights: min, max, mean, population std
+        std::vector<int> col(p.N, 0), row(p.M, 0);
+        for (int r = 0; r < p.M; r++)
+            for (int i = 0; i < p.N; i++)
+                if (p.rows[r].get(i)) {
+                    col[i]++;
+                    row[r]++;
+                }
+        auto fill = [](const std::vector<int> &w, double *o) {
+            double s = 0.0, s2 = 0.0;
+            int lo = w[0], hi = w[0];
+            for (int v : w) {
+                s += v;
+                lo = std::min(lo, v);
+                hi = std::max(hi, v);
+            }
+            const double mean = s / (double)w.size();
+            for (int v : w)
+                s2 += (v - mean) * (v - mean);
+            o[0] = lo;
+            o[1] = hi;
+            o[2] = mean;
+            o[3] = std::sqrt(s2 / (double)w.size());
+        };
+        fill(col, wstats);
+        fill(row, wstats + 4);
+    }
+    return BCH_OK;
+}
+
 int bch_pcm_export(bch_pcm pcm, uint8_t *dense, size_t cap)
 {
     if (!pcm || !dense)
@@ -336,6 +380,25 @@ int bch_make_automorphisms(int N, int n_branches, int d_o, int16_t *maps)
     int rc = branch_maps(N, n_branches, d_o, maps);
     if (rc)
         return fail(rc, "n_branches must be 1, 3 or 9 and d_o in [0, d_p)");
+    return BCH_OK;
+}
+
+int bch_draw_offsets(int N, uint64_t seed, uint64_t key_hi, int64_t frame_base, int64_t F, uint8_t *d_o,
+                     int on_device, hipStream_t stream)
+{
+    if (N < 7 || N > 127 || F < 0 || frame_base < 0)
+        return fail(BCH_EINVAL, "bad argument (7 <= N <= 127, F >= 0, frame_base >= 0)");
+    if (F == 0)
+        return BCH_OK;
+    if (!d_o)
+        return fail(BCH_EINVAL, "d_o is NULL");
+    const int dp = shift_period(N);
+    if (on_device) {
+        hipError_t e = launch_draw_offsets(seed, key_hi, frame_base, F, dp, d_o, stream);
+        return e == hipSuccess ? BCH_OK : hip_fail(e, "offset draw kernel launch");
+    }
+    for (int64_t f = 0; f < F; f++)
+        d_o[f] = draw_offset(seed, key_hi, (uint64_t)(frame_base + f), dp);
     return BCH_OK;
 }
 

@@ -14,6 +14,7 @@
 #include <cstdint>
 
 #include "kernels.h"
+#include "philox.h"
 
 namespace bch {
 
@@ -52,7 +53,8 @@ __global__ void __launch_bounds__(WAVE) nms_generic_fp32(GenericArgs a)
         ys[u * WAVE + lane] = live ? llr[f * a.ld + u] + 0.0f : 1.0f;
     const int B = a.B;
     const int dp = a.dp;
-    const int d_o = (live && B > 1) ? (int)a.d_o[f] : 0;
+    // d_o is taken modulo d_p, as by the specialised kernels' bucketing
+    const int d_o = (live && B > 1) ? (int)a.d_o[f] % dp : 0;
     const int np = (B == 9) ? 3 : 1;
     const int mult[3] = {1, 2, (N + 1) / 2};
     bool done = !live;
@@ -172,15 +174,31 @@ __global__ void quantize_kernel(const float *__restrict__ llr, int64_t ld, int64
         return;
     int8_t out = 0;
     if (i < N) {
-        const float x = llr[f * ld + i] * scale;
-        float r = floorf(fabsf(x) + 0.5f);
-        r = fminf(r, 127.0f);
-        out = (int8_t)(int)(x < 0.0f ? -r : r);
+        // roundf rounds half away from zero without forming |x| + 0.5 (which
+        // itself rounds, e.g. 0.49999997 + 0.5 = 1.0 in FP32)
+        const float r = fminf(fmaxf(roundf(llr[f * ld + i] * scale), -127.0f), 127.0f);
+        out = (int8_t)(int)r;
     }
     q[f * ldq + i] = out;
 }
 
+__global__ void draw_offsets_kernel(uint64_t seed, uint64_t key_hi, int64_t base, int64_t F, int dp,
+                                    uint8_t *__restrict__ d_o)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < F)
+        d_o[f] = draw_offset(seed, key_hi, (uint64_t)(base + f), dp);
+}
+
 }  // namespace
+
+hipError_t launch_draw_offsets(uint64_t seed, uint64_t key_hi, int64_t base, int64_t F, int dp, uint8_t *d_o,
+                               hipStream_t stream)
+{
+    const dim3 grid((unsigned)((F + 255) / 256));
+    hipLaunchKernelGGL(draw_offsets_kernel, grid, dim3(256), 0, stream, seed, key_hi, base, F, dp, d_o);
+    return hipGetLastError();
+}
 
 hipError_t launch_generic_fp32(const GenericArgs &a, hipStream_t stream)
 {

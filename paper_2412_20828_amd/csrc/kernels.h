@@ -33,6 +33,9 @@ struct GenericArgs {
 hipError_t launch_generic_fp32(const GenericArgs &a, hipStream_t stream);
 hipError_t launch_syndrome(const uint64_t *bits, int64_t F, int W64, const uint64_t *hsyn,
                            int msyn, uint8_t *ok, hipStream_t stream);
+// d_o[f] = draw_offset(seed, key_hi, base + f, dp) for f < F (device buffer)
+hipError_t launch_draw_offsets(uint64_t seed, uint64_t key_hi, int64_t base, int64_t F, int dp, uint8_t *d_o,
+                               hipStream_t stream);
 hipError_t launch_quantize(const float *llr, int64_t ld, int64_t F, int N, float scale,
                            int8_t *q, int64_t ldq, hipStream_t stream);
 

@@ -55,7 +55,7 @@ def hw_queues(n_slots: int, n_codes: int) -> int:
 class Request:
     code: int                  # index into the engine's code list
     llr: np.ndarray            # [F][ld] float32 channel LLRs (host)
-    d_o: np.ndarray            # [F] uint8 cyclic offsets
+    d_o: np.ndarray = None     # [F] uint8 cyclic offsets in [0, d_p), or None: drawn by the engine
     rid: int = 0
     arrival: float = 0.0       # time.perf_counter() at submission (set by submit when 0)
     bits: np.ndarray = None    # [F][2] uint64 decisions (bit i of word i // 64)
@@ -103,8 +103,9 @@ class Engine:
     autotuner's cached launch shapes."""
 
     def __init__(self, codes, slot_frames=1 << 16, n_slots=3, osd_order=2, osd_on="device", osd_threads=8,
-                 precision=B.FP32, max_iter=8, tuned=True, device="cuda"):
+                 precision=B.FP32, max_iter=8, tuned=True, device="cuda", seed=0):
         import torch
+        self.seed = seed  # key of the offsets the engine draws (bch_draw_offsets)
         self.torch = torch
         self.dev = torch.device(device)
         self.names = [n for n, _ in codes]
@@ -166,11 +167,27 @@ class Engine:
             raise B.BchError("unknown code index %d" % req.code)
         if req.frames > self.cap:
             raise B.BchError("request of %d frames exceeds the slot capacity %d" % (req.frames, self.cap))
-        if req.llr.shape[1] < self.codes[req.code][0].N:
+        N = self.codes[req.code][0].N
+        if req.llr.shape[1] < N:
             raise B.BchError("LLR rows shorter than the code length")
+        if req.d_o is not None:
+            if req.d_o.shape != (req.frames,):
+                raise B.BchError("d_o must hold one offset per frame")
+            if req.frames and int(req.d_o.max()) >= B.shift_period(N):
+                raise B.BchError("d_o must lie in [0, d_p) = [0, %d)" % B.shift_period(N))
         if not req.arrival:
             req.arrival = time.perf_counter()
         self.pending.append(req)
+
+    def draw_offsets(self, req: Request, out=None):
+        """The random offsets of a request that brings none: the library's
+        draw keyed by (engine seed, request id), frame uid = index in the
+        request, so a request's frames get the same offsets alone and in any
+        mix."""
+        N = self.codes[req.code][0].N
+        if out is None:
+            return B.draw_offsets(N, self.seed, req.rid, 0, req.frames)
+        return B.draw_offsets(N, self.seed, req.rid, 0, req.frames, out=out)
 
     def busy(self) -> bool:
         return bool(self.pending or self.osd_jobs or any(s.busy for s in self.slots))
@@ -232,7 +249,10 @@ class Engine:
         for r in take:
             off, F, w = pos[r.code], r.frames, min(r.llr.shape[1], self.ld)
             hl[off:off + F, :w] = r.llr[:, :w]
-            hd[off:off + F] = r.d_o
+            if r.d_o is None:
+                self.draw_offsets(r, hd[off:off + F])
+            else:
+                hd[off:off + F] = r.d_o
             r.t_admit = now
             s.members.append((r, off))
             pos[r.code] += F
@@ -319,7 +339,8 @@ def decode_alone(engine: Engine, req: Request):
     dec = engine.decs[req.code]
     code = engine.codes[req.code][0]
     llr = torch.from_numpy(np.ascontiguousarray(req.llr)).to(engine.dev)
-    d_o = torch.from_numpy(np.ascontiguousarray(req.d_o)).to(engine.dev)
+    d_h = req.d_o if req.d_o is not None else engine.draw_offsets(req)
+    d_o = torch.from_numpy(np.ascontiguousarray(d_h)).to(engine.dev)
     bits, iters, flags, _ = dec.decode(llr, d_o)
     torch.cuda.synchronize()
     F = req.frames

@@ -11,7 +11,12 @@ oracle's code construction.
 Randomness: numpy's Philox counter-based generator, keyed by a SeedSequence of
 (seed, code tag, stream, block) so that any block of frames is reproducible on
 its own (a request's frames are the same alone and in a mix).
-Streams: 0 information bits, 1 noise, 2 d_o, 3 mixed-workload draws.
+Streams: 0 information bits, 1 noise, 3 mixed-workload draws, 4 arrivals.
+The offsets d_o follow the draw the decoder library offers
+(bch_draw_offsets): word 0 of Philox4x64-10 at counter (frame uid, 0, 0, 0)
+under key (seed, code tag << 32 | block), mapped to [0, d_p) by
+((word >> 32) d_p) >> 32; here numpy's own Philox bit generator produces the
+words.
 """
 from __future__ import annotations
 
@@ -77,6 +82,25 @@ def sigma2_of(ebn0_db, rate):
     return 1.0 / (2.0 * rate * 10.0 ** (np.asarray(ebn0_db, dtype=np.float64) / 10.0))
 
 
+def offsets(N: int, seed: int, key_hi: int, F: int, frame_base: int = 0) -> np.ndarray:
+    """d_o of frames frame_base .. frame_base + F - 1: word 0 of Philox4x64-10
+    at counter (uid, 0, 0, 0) under key (seed, key_hi), scaled to [0, d_p).
+    numpy's Philox advances its counter before each block of four words, so it
+    starts one step before frame_base (all ones wraps to zero)."""
+    dp = 21 if N == 63 else (42 if N == 127 else N // 3)
+    m64 = (1 << 64) - 1
+    start = [frame_base - 1, 0, 0, 0] if frame_base > 0 else [m64] * 4
+    bg = np.random.Philox(counter=np.array(start, dtype=np.uint64),
+                          key=np.array([seed & m64, key_hi & m64], dtype=np.uint64))
+    w = bg.random_raw(4 * F)[0::4] if F else np.zeros(0, np.uint64)
+    return (((w >> np.uint64(32)) * np.uint64(dp)) >> np.uint64(32)).astype(np.uint8)
+
+
+def offset_key(name: str, block: int) -> int:
+    """key_hi of a code's frames in one block: code tag << 32 | block."""
+    return (CODE_TAG[name] << 32) | (block & 0xFFFFFFFF)
+
+
 def _rng(seed: int, tag: int, stream: int, block: int) -> np.random.Generator:
     return np.random.Generator(np.random.Philox(np.random.SeedSequence([seed, tag, stream, block])))
 
@@ -135,7 +159,7 @@ def frames(name: str, F: int, ebn0, seed: int, block: int = 0, zero_codeword: bo
     y = (1.0 - 2.0 * cw.astype(np.float32)) + np.sqrt(s2) * noise
     llr = np.zeros((F, ld), dtype=np.float32)
     llr[:, :N] = (2.0 / s2) * y
-    d_o = _rng(seed, tag, 2, block).integers(0, spec.d_p, size=F, dtype=np.uint8)
+    d_o = offsets(N, seed, offset_key(name, block), F)
     return Frames(llr, cw, d_o, e)
 
 

@@ -108,3 +108,31 @@ def test_argument_errors_are_reported(B):
     c = B.Code(d.m, d.prim, d.t)
     p = B.Pcm.standard(c)
     assert p.M == 18 and p.E == 18 * 24
+
+
+@pytest.mark.parametrize("N", [63, 127, 15])
+def test_host_offset_draw_matches_oracle(B, N):
+    for seed, key_hi, base, F in [(0, 0, 0, 1000), (2 ** 63 + 5, 77, 123456789, 300), (1, (3 << 32) | 9, 5, 1)]:
+        got = B.draw_offsets(N, seed, key_hi, base, F)
+        assert np.array_equal(got, oracle.draw_offsets(N, seed, key_hi, base, F))
+    with pytest.raises(B.BchError):
+        B.draw_offsets(N, 0, 0, -1, 4)
+
+
+def test_synth_offsets_follow_the_library_draw(B):
+    fr = synth.frames("bch63_36", 500, 3.0, seed=12, block=4)
+    assert np.array_equal(fr.d_o, B.draw_offsets(63, 12, synth.offset_key("bch63_36", 4), 0, 500))
+
+
+@pytest.mark.parametrize("name", list(HO_ROWS))
+def test_pcm_stats_match_oracle(B, name):
+    d = B.CODE_DEFS[name]
+    c = B.Code(d.m, d.prim, d.t)
+    for p in (B.Pcm.standard(c), B.Pcm.build(c, target_rows=HO_ROWS[name], seed=1)):
+        got = p.stats()
+        want = oracle.pcm_stats(p.dense())
+        assert (got["M"], got["E"], got["c4"]) == (want["M"], want["edges"], want["c4"])
+        for k in ("col_range", "row_range"):
+            assert tuple(got[k]) == tuple(want[k])
+        for k in ("col_mean", "col_std", "row_mean", "row_std"):
+            assert abs(got[k] - want[k]) < 1e-12

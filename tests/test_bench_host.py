@@ -21,10 +21,33 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_work_model_per_frame_iteration():
-    # 8 B E + 2 B M + 2 B N + 2 (N - K) ceil(N / 64), nine branches
-    assert bench.alg_ops_per_iteration(63, 45, 33, 528, 9) == 8 * 9 * 528 + 2 * 9 * 33 + 2 * 9 * 63 + 2 * 18
-    assert bench.alg_ops_per_iteration(63, 36, 122, 1867, 9) == 137808
-    assert bench.alg_ops_per_iteration(127, 64, 72, 1598, 9) == 8 * 9 * 1598 + 2 * 9 * 72 + 2 * 9 * 127 + 2 * 63 * 2
+    # restart mode: 7 B E + 2 B M + 2 B N + 2 (N - K) ceil(N / 64), nine branches
+    assert bench.alg_ops_per_iteration(63, 45, 33, 528, 9) == 7 * 9 * 528 + 2 * 9 * 33 + 2 * 9 * 63 + 2 * 18
+    assert bench.alg_ops_per_iteration(63, 36, 122, 1840, 9) == 7 * 9 * 1840 + 2 * 9 * 122 + 2 * 9 * 63 + 2 * 27
+    assert bench.alg_ops_per_iteration(127, 64, 72, 1598, 9) == 7 * 9 * 1598 + 2 * 9 * 72 + 2 * 9 * 127 + 2 * 63 * 2
+    # the extrinsic mode adds the v2c subtraction, the memory mode two operations per edge
+    base = bench.alg_ops_per_iteration(63, 36, 27, 486, 1)
+    assert bench.alg_ops_per_iteration(63, 36, 27, 486, 1, mode=3) == base + 486
+    assert bench.alg_ops_per_iteration(63, 36, 27, 486, 1, mode=2) == base + 2 * 486
+
+
+def test_table2_complexity_ratios():
+    """The paper's Table 2: every printed ratio from automorphisms x iterations
+    x rows (x parallel decoders) over mRRD(1) on the 18-row (63,45) matrix,
+    to the printed digits; and the enhanced NMS row from this decoder's own
+    configuration (nine branches, I_m = 4 for length 63, the 33-row H_o of
+    (63,45))."""
+    import json
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "table2_complexity.json")))
+    ref = gold["reference"]
+    assert (ref["automorphisms"], ref["iterations"], ref["M_s"]) == bench.TABLE2_REFERENCE
+    for row in gold["rows"]:
+        r = bench.table2_complexity(row["automorphisms"], row["iterations"], row["M_s"], row["parallel"])
+        digits = len(str(row["ratio"]).split(".")[1].lstrip("0"))  # printed significant digits
+        assert float("%.*g" % (digits, r)) == row["ratio"], (row, r)
+    from tests.helpers import HO_ROWS
+    nine, im = 9, 4
+    assert round(bench.table2_complexity(nine, im, HO_ROWS["bch63_45"]), 3) == 0.088
 
 
 def test_pack_matches_bit_order():

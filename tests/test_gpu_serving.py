@@ -25,12 +25,13 @@ def S():
     return serving
 
 
-def make_requests(S, n, seed, max_log2=12):
+def make_requests(S, n, seed, max_log2=12, engine_offsets=False):
+    """engine_offsets: the requests bring no d_o; the engine draws them."""
     tr = synth.request_trace(n, seed, len(NAMES), 2.0, 5.0, max_log2=max_log2)
     reqs, cws = [], []
     for k, d in enumerate(tr):
         fr = synth.request_frames(NAMES, d, seed, k)
-        reqs.append(S.Request(code=d.code, llr=fr.llr, d_o=fr.d_o, rid=k))
+        reqs.append(S.Request(code=d.code, llr=fr.llr, d_o=None if engine_offsets else fr.d_o, rid=k))
         cws.append(fr.codewords)
     return tr, reqs, cws
 
@@ -47,9 +48,12 @@ def test_served_results_equal_alone(S, osd_on):
     """Requests arriving at 20,000/s (several in flight on separate slots):
     every frame's decision, iteration count and flags equal those of the
     request decoded alone (its code's decoder, then host OSD-2 on its
-    failures), with the service's OSD stage on the device or on the host."""
-    eng = S.Engine(SERVE_CODES, slot_frames=8192, n_slots=3, osd_order=2, osd_on=osd_on, osd_threads=4)
-    tr, reqs, cws = make_requests(S, 48, 7)
+    failures), with the service's OSD stage on the device or on the host.
+    With OSD on the device the requests bring no offsets: the engine draws
+    them through the library, keyed by request id, and the alone decode
+    draws the same."""
+    eng = S.Engine(SERVE_CODES, slot_frames=8192, n_slots=3, osd_order=2, osd_on=osd_on, osd_threads=4, seed=3)
+    tr, reqs, cws = make_requests(S, 48, 7, engine_offsets=osd_on == "device")
     done, wall = S.run_trace(eng, reqs, [d.t / 20000.0 for d in tr])
     assert len(done) == len(reqs) and eng.launches >= 2
     n_osd = 0
@@ -120,3 +124,16 @@ def test_admission_and_overlap(S):
         eng.submit(big)
     with pytest.raises(Exception):
         eng.submit(S.Request(code=9, llr=np.zeros((1, 128), np.float32), d_o=np.zeros(1, np.uint8)))
+    with pytest.raises(S.B.BchError):  # offsets outside [0, d_p)
+        eng.submit(S.Request(code=2, llr=np.zeros((2, 128), np.float32), d_o=np.array([0, 42], np.uint8)))
+
+
+def test_engine_offsets_follow_the_library_draw(S):
+    """The engine's offsets of a request equal the oracle's Philox draw under
+    the same key (engine seed, request id), and lie in [0, d_p)."""
+    eng = S.Engine(SERVE_CODES[:1] + SERVE_CODES[2:3], slot_frames=4096, n_slots=1, osd_order=None, seed=77)
+    for code, N, dp in ((0, 63, 21), (1, 127, 42)):
+        r = S.Request(code=code, llr=np.zeros((1000, 128), np.float32), rid=12345 + code)
+        d = eng.draw_offsets(r)
+        assert np.array_equal(d, oracle.draw_offsets(N, 77, 12345 + code, 0, 1000))
+        assert d.max() < dp and len(set(d.tolist())) == dp

@@ -183,9 +183,10 @@ def test_enhanced_beats_plain_nms_statistically():
 
 # --------------------------------------------------------------- fixed point
 def test_quantize_rounding_and_clamp():
-    L = np.array([0.125, 0.124, -0.125, -0.126, 31.6, -40.0, 0.0, 31.874], dtype=np.float32)
+    below = float(np.nextafter(np.float32(0.125), np.float32(0)))  # x 4 = 0.49999997: rounds to 0
+    L = np.array([0.125, 0.124, -0.125, -0.126, 31.6, -40.0, 0.0, 31.874, below, -below], dtype=np.float32)
     q = oracle.quantize(L, 4.0)
-    assert list(q) == [1, 0, -1, -1, 126, -127, 0, 127]
+    assert list(q) == [1, 0, -1, -1, 126, -127, 0, 127, 0, 0]
 
 
 def test_fixed_point_saturation_and_range():
@@ -286,3 +287,24 @@ def test_osd_output_is_codeword():
         L = rng.standard_normal(63) * 2 + 1
         w = oracle.osd(c.G, L, 2)
         assert not ((c.Hstd.astype(int) @ w.astype(int)) % 2).any()
+
+
+def test_hand_worked_fixed_point_three_branches():
+    """B = 3 integer decoder against a hand-worked trajectory: v2c saturation
+    at 127, the branch average rounding down and up, a positive average, then
+    the closed form y^(t) = y^(4) - 63 (t - 4) until the posterior saturates
+    at -32767 and stays there."""
+    g = json.load(open(os.path.join(GOLD, "fixed_point_b3_hand.json")))
+    H = np.array(g["H"], dtype=np.uint8)
+    Hs = np.array(g["Hsyn"], dtype=np.uint8)
+    maps = np.array(g["maps"], dtype=np.int16)
+    r = oracle.nms_fixed(H, maps, np.array(g["q"], dtype=np.int8), g["max_iter"], oracle.R1, Hs, trace=True)
+    assert r["iters"] == g["iters"] and r["converged"] == g["converged"]
+    assert list(r["c_hat"]) == g["c_hat"]
+    tr = r["y_trace"]
+    first = np.array(g["y_first"])
+    assert np.array_equal(tr[:4], first)
+    t = np.arange(5, g["max_iter"] + 1)[:, None]
+    want = np.maximum(first[3][None, :] + g["step_after"] * (t - 4), g["saturation"])
+    assert np.array_equal(tr[4:], want)
+    assert tr[519, 0] == -32723 and tr[520, 0] == -32767 and tr[520, 1] > -32767  # t = 520, 521

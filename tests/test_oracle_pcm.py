@@ -71,21 +71,48 @@ def test_build_hopt_validity(NK, beta, target):
     assert len({tuple(r) for r in H}) == H.shape[0]
 
 
-def test_build_hopt_against_table1_targets():
+# Recorded deviation from Table 1: for (127,64) the step-3 reading used here
+# finds 18 cyclic classes (7 of weight 22, 10 of 24, 1 of 26) where Table 1
+# implies 54, mostly of weight 22; padded to 72 rows the matrix keeps its
+# weight-26 class and has about a third more length-4 cycles.
+TABLE1_DEVIATIONS = {(127, 64): {"row_max": 26, "c4_rel": 0.35}}
+
+
+@pytest.mark.parametrize("idx", range(7))
+def test_build_hopt_against_table1_targets(idx):
+    """Every optimised matrix of Table 1 at the printed dimensions: exact row
+    count, rows in the dual, full rank, row weights in the printed range and
+    length-4 cycles within 15% of the paper's annealed matrix -- except the
+    recorded (127,64) deviation, bounded here."""
     gold = json.load(open(os.path.join(GOLD, "table1_optimized_h.json")))
-    for row in gold["codes"]:
-        if row["N"] == 127 and row["K"] != 99:
-            continue  # covered by the length-127 H_o test in the slow set
-        c = code(row["N"], row["K"])
-        H, mr1, _ = oracle.build_hopt(c, target_rows=row["M_o"], seed=1)
-        s = oracle.pcm_stats(H)
-        assert s["M"] == row["M_o"]
-        lo, hi = row["row_range"]
-        assert s["row_range"][0] >= lo and s["row_range"][1] <= hi
-        # length-4 cycles within 15% of the paper's annealed result
-        assert abs(s["c4"] - row["c4"]) <= 0.15 * row["c4"], (row, s)
-        if (row["N"], row["K"]) == (63, 45):
-            assert mr1 == row["M_r1"]
+    row = gold["codes"][idx]
+    c = code(row["N"], row["K"])
+    H, mr1, _ = oracle.build_hopt(c, target_rows=row["M_o"], seed=1)
+    s = oracle.pcm_stats(H)
+    assert s["M"] == row["M_o"]
+    assert oracle.rank(H) == c.N - c.K
+    assert not ((c.G.astype(int) @ H.T.astype(int)) % 2).any()
+    lo, hi = row["row_range"]
+    dev = TABLE1_DEVIATIONS.get((row["N"], row["K"]))
+    assert s["row_range"][0] >= lo
+    assert s["row_range"][1] <= (dev["row_max"] if dev else hi)
+    rel = abs(s["c4"] - row["c4"]) / row["c4"]
+    assert rel <= (dev["c4_rel"] if dev else 0.15), (row, s)
+    if (row["N"], row["K"]) == (63, 45):
+        assert mr1 == row["M_r1"]
+
+
+def test_dual_low_weight_classes_of_63_36():
+    """Evidence on the step-3 reading (brute force over the 2^27 dual words):
+    the (63,36) dual has 450 words of weight 14 in 8 cyclic classes and 11,025
+    of weight 16 in 175 classes.  Table 1 implies M_r1 = 22, so H_r1 is
+    neither every minimum-weight class (8) nor every class of the two lowest
+    weights (183, what collecting all of S_f into S_g gives)."""
+    c = code(63, 36)
+    A = oracle.weight_distribution(c.Hstd)
+    assert int(A[0]) == 1 and not A[1:14].any() and int(A[14]) == 450 and int(A[16]) == 11025
+    W = oracle.words_of_weight(c.Hstd, 14)
+    assert len({min(tuple(np.roll(w, q)) for q in range(63)) for w in W}) == 8
 
 
 def test_build_hopt_deterministic_in_seed():
@@ -143,3 +170,40 @@ def test_branch_map_definitions():
     assert list(maps[3]) == [(j - 26) % N for j in range(N)]
     assert list(maps[6]) == [(j - 47) % N for j in range(N)]
     assert list(oracle.branch_maps(N, 1, 0)[0]) == list(range(N))
+
+
+# ------------------------------------------------------------ offset draw
+def test_philox_matches_numpy_generator():
+    """The oracle's Philox4x64-10 block equals numpy's Philox bit generator,
+    an independent implementation of the same published definition (numpy
+    advances its counter before producing each block of four words)."""
+    m64 = (1 << 64) - 1
+    rng = np.random.default_rng(2024)
+    for _ in range(20):
+        key = [int(v) for v in rng.integers(0, 2 ** 63, 2, dtype=np.int64)]
+        ctr = [int(v) for v in rng.integers(0, 2 ** 63, 4, dtype=np.int64)]
+        bg = np.random.Philox(counter=np.array([(ctr[0] - 1) & m64] + ctr[1:], dtype=np.uint64),
+                              key=np.array(key, dtype=np.uint64))
+        want = [int(v) for v in bg.random_raw(4)]
+        assert oracle.philox4x64_10(ctr, key) == want
+    # counter word 0 wrapping into word 1
+    bg = np.random.Philox(counter=np.array([m64 - 1, 5, 0, 0], dtype=np.uint64), key=np.array([3, 4], np.uint64))
+    bg.random_raw(4)
+    assert oracle.philox4x64_10([0, 6, 0, 0], [3, 4]) == [int(v) for v in bg.random_raw(4)]
+
+
+@pytest.mark.parametrize("N,dp", [(63, 21), (127, 42)])
+def test_offset_draw_definition_and_uniformity(N, dp):
+    """d_o = ((word0 >> 32) d_p) >> 32 of the frame's own counter: a frame's
+    offset does not depend on the batch it is drawn in, and the offsets are
+    uniform over [0, d_p) (chi-square over 200,000 frames)."""
+    a = oracle.draw_offsets(N, 9, 4, 0, 200_000)
+    b = oracle.draw_offsets(N, 9, 4, 1000, 50)
+    assert np.array_equal(a[1000:1050], b)
+    w = oracle.philox4x64_10([1234, 0, 0, 0], [9, 4])[0]
+    assert a[1234] == ((w >> 32) * dp) >> 32
+    cnt = np.bincount(a, minlength=dp)
+    assert cnt.size == dp
+    exp = a.size / dp
+    chi2 = float(((cnt - exp) ** 2 / exp).sum())
+    assert chi2 < 80.0  # dp - 1 = 20 or 41 degrees of freedom

@@ -38,3 +38,46 @@ def test_one_step_check_catches_a_perturbed_iteration():
     g_tr[f, 1, 7] += np.float32(1e-4 * scale)  # iteration 2 of frame f, one coordinate
     with pytest.raises(AssertionError):
         compare_with_oracle(c, it, cv, g_tr, *res, onestep=onestep)
+
+
+def test_decision_flip_without_tie_is_caught():
+    """A frame whose decoded word differs while the oracle's posterior never
+    comes near zero is not a tie, with or without the GPU trace."""
+    g, res, onestep = _run()
+    c, it, cv, g_tr = g
+    tr = res[3]
+    rho = np.array([np.nanmin(np.abs(tr[f, :it[f]]) / np.nanmax(np.abs(tr[f, :it[f]]), axis=1, keepdims=True))
+                    for f in range(len(it))])
+    f = int(np.argmax(rho > 1e-3))
+    assert rho[f] > 1e-3
+    bad = c.copy()
+    bad[f, 3] ^= 1
+    with pytest.raises(AssertionError, match="without a tie"):
+        compare_with_oracle(bad, it, cv, None, *res)
+    g2 = g_tr.copy()
+    g2[f, 0, :] = -g2[f, 0, :]  # every decision of iteration 1 flipped
+    with pytest.raises(AssertionError, match="without a tie"):
+        compare_with_oracle(bad, it, cv, g2, *res)
+
+
+def test_near_zero_after_the_divergence_does_not_excuse():
+    """Hand-made 7-coordinate frame: the GPU's decision differs at iteration
+    1, where every oracle |y| is at least half the largest; the oracle's only
+    near-zero value comes at iteration 3, after the divergence."""
+    N, T = 7, 3
+    tr = np.array([[[4.0, -3.0, 2.5, 3.0, -2.0, 5.0, 2.0],
+                    [5.0, -4.0, 3.0, 3.5, -2.5, 6.0, 2.5],
+                    [6.0, -5.0, 1e-9, 4.0, -3.0, 7.0, 3.0]]])
+    orc_c = (tr[:, -1] < 0).astype(np.uint8)
+    orc_it, orc_cv = np.array([T]), np.array([False])
+    g = np.zeros((1, T, 8), np.float32)
+    g[0, :, :N] = tr[0]
+    g[0, 0, 2] = -2.5  # flipped at iteration 1
+    gw = orc_c.copy()
+    gw[0, 2] ^= 1
+    with pytest.raises(AssertionError, match="without a tie"):
+        compare_with_oracle(gw, orc_it, np.array([0]), g, orc_c, orc_it, orc_cv, tr)
+    # the same flip at iteration 3, where the oracle value is within 1e-5 of zero, is a tie
+    g[0, 0, 2] = 2.5
+    g[0, 2, 2] = -1e-9
+    assert compare_with_oracle(gw, orc_it, np.array([0]), g, orc_c, orc_it, orc_cv, tr) == (1, 1)
