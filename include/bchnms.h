@@ -197,6 +197,23 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
                          uint8_t *flags, void *y_trace, void *workspace,
                          size_t ws_bytes, hipStream_t stream);
 
+/* Allocation-free form of bch_nms_decode_batch, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same decode and results, with the
+ * workspace taken from a device array that the library holds for each GPU it
+ * runs on (BCH_NOALLOC_SCRATCH_BYTES, until the process ends; its address is
+ * looked up on the first call on a device).  The call allocates nothing and
+ * clears nothing (the bucketing prepass writes every workspace byte it later
+ * reads).  A decode whose bch_decode_workspace_size exceeds the scratch (a
+ * specialised decoder above 4,194,304 frames, an edge-memory mode of the
+ * generic kernel on more than a few frames) returns BCH_EINVAL.  Every call
+ * on one GPU shares that GPU's scratch: calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller. */
+#define BCH_NOALLOC_SCRATCH_BYTES ((size_t)17 << 20)
+int bch_nms_decode_batch_noalloc(bch_decoder dec, const void *llr, int64_t ld, int64_t F, const uint8_t *d_o,
+                                 uint64_t *bits, uint8_t *iters, uint8_t *flags, void *y_trace,
+                                 hipStream_t stream);
+
 /* Tuning of a specialised decoder (autotuner hook): waves per CU of the
  * persistent grid (0: the kernel's default; the nine-branch N = 63 kernels
  * run workgroups of three waves, so waves_per_cu / 3 of them per CU).  A

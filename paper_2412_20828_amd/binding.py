@@ -33,7 +33,7 @@ SYMBOLS = [
     "bch_decoder_destroy", "bch_decode_workspace_size", "bch_nms_decode_batch",
     "bch_syndrome_check", "bch_quantize_llr", "bch_osd_decode", "bch_decoder_set_tuning",
     "bch_mixed_workspace_size", "bch_mixed_decode_batch", "bch_osd_decode_device", "bch_mixed_osd_decode",
-    "bch_draw_offsets", "bch_pcm_stats",
+    "bch_draw_offsets", "bch_pcm_stats", "bch_nms_decode_batch_noalloc",
 ]
 MAX_MIX = 8
 
@@ -93,6 +93,7 @@ def lib():
     L.bch_decode_workspace_size.argtypes = [P, i64]
     L.bch_decode_workspace_size.restype = ctypes.c_size_t
     L.bch_nms_decode_batch.argtypes = [P, P, i64, i64, P, P, P, P, P, P, ctypes.c_size_t, P]
+    L.bch_nms_decode_batch_noalloc.argtypes = [P, P, i64, i64, P, P, P, P, P, P]
     L.bch_syndrome_check.argtypes = [P, P, i64, P, P]
     L.bch_quantize_llr.argtypes = [P, i64, i64, i32, ctypes.c_float, P, i64, P]
     L.bch_osd_decode.argtypes = [P, P, i64, i64, i32, P, P, i32]
@@ -263,6 +264,14 @@ class Decoder:
         _check(lib().bch_nms_decode_batch(self.h, _dptr(llr), ld, F, _dptr(d_o), _dptr(bits), _dptr(iters),
                                           _dptr(flags), _dptr(y_trace), _dptr(workspace), ws_bytes,
                                           _stream(stream)), "bch_nms_decode_batch")
+
+    def decode_noalloc(self, llr, d_o, bits, iters, flags, y_trace=None, stream=None):
+        """Enqueue bch_nms_decode_batch_noalloc (workspace from the library's
+        device scratch; nothing allocated)."""
+        F, ld = llr.shape
+        _check(lib().bch_nms_decode_batch_noalloc(self.h, _dptr(llr), ld, F, _dptr(d_o), _dptr(bits), _dptr(iters),
+                                                  _dptr(flags), _dptr(y_trace), _stream(stream)),
+               "bch_nms_decode_batch_noalloc")
 
     def decode(self, llr, d_o=None, trace=False, stream=None):
         """Allocate outputs (and workspace) with torch and decode."""

@@ -27,7 +27,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
 HOST_SRCS = ["host_code.cpp", "host_pcm.cpp", "host_osd.cpp", "capi.cpp", "spec_registry.cpp"]
-HIP_SRCS = ["k_generic.hip", "k_bucket.hip", "k_osd.hip"]
+HIP_SRCS = ["k_generic.hip", "k_bucket.hip", "k_osd.hip", "noalloc.hip"]
 
 CXXFLAGS = ["-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",
             "-D__HIP_PLATFORM_AMD__", "-I" + INCLUDE, "-I" + CSRC, "-I" + os.path.join(ROCM, "include")]

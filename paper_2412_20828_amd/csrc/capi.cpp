@@ -171,6 +171,8 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
 
 using namespace bch;
 
+static_assert(BCH_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes, "scratch size of the header and the library");
+
 extern "C" {
 
 const char *bch_last_error(void) { return g_err.c_str(); }
@@ -585,6 +587,30 @@ int bch_nms_decode_batch(bch_decoder dec, const void *llr, int64_t ld, int64_t F
     a.ws_s = ws ? ws + (size_t)a.B * a.E * F : nullptr;
     hipError_t e = launch_generic_fp32(a, stream);
     return e == hipSuccess ? BCH_OK : hip_fail(e, "generic kernel launch");
+}
+
+int bch_nms_decode_batch_noalloc(bch_decoder dec, const void *llr, int64_t ld, int64_t F, const uint8_t *d_o,
+                                 uint64_t *bits, uint8_t *iters, uint8_t *flags, void *y_trace, hipStream_t stream)
+{
+    if (!dec)
+        return fail(BCH_EINVAL, "decoder is NULL");
+    if (F < 0 || F > BCH_MAX_FRAMES)
+        return fail(BCH_EINVAL, "F out of range");
+    const size_t need = bch_decode_workspace_size(dec, F);
+    if (need > BCH_NOALLOC_SCRATCH_BYTES)
+        return fail(BCH_EINVAL, "decode of " + std::to_string(F) + " frames needs " + std::to_string(need) +
+                                    " bytes of workspace, above the " + std::to_string(BCH_NOALLOC_SCRATCH_BYTES) +
+                                    "-byte device scratch of the allocation-free entry point");
+    void *ws = nullptr;
+    if (need) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != dec->dev)
+            return fail(BCH_EINVAL, "decoder belongs to another device");
+        hipError_t e = noalloc_scratch(&ws);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress of the decode scratch");
+    }
+    return bch_nms_decode_batch(dec, llr, ld, F, d_o, bits, iters, flags, y_trace, ws, need, stream);
 }
 
 int bch_decoder_set_tuning(bch_decoder dec, int waves_per_cu)

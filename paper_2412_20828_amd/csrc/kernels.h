@@ -30,6 +30,13 @@ struct GenericArgs {
     float *ws_s;            // [2][B][N][F] (memory mode R2)
 };
 
+// Device scratch of the allocation-free decode (one array per GPU, 17 MiB:
+// the workspace of a specialised decode of up to 4,194,304 frames).
+constexpr size_t kNoAllocScratchBytes = (size_t)17 << 20;
+// address of the calling thread's current device's scratch (looked up once per
+// device with hipGetSymbolAddress)
+hipError_t noalloc_scratch(void **ptr);
+
 hipError_t launch_generic_fp32(const GenericArgs &a, hipStream_t stream);
 hipError_t launch_syndrome(const uint64_t *bits, int64_t F, int W64, const uint64_t *hsyn,
                            int msyn, uint8_t *ok, hipStream_t stream);
