@@ -1,37 +1,43 @@
 """Throughput of enhanced normalized min-sum decoding of short BCH codes on
 one MI355X.
 
-Default workload "sweep63" (one "step" = one pass of the whole decode path
-over the batch): BCH(63,45) with the optimised 33 x 63 H_o and BCH(63,36) with the optimised
-122 x 63 H_o; enhanced NMS with the 9-branch automorphism block (three random
-cyclic shifts of y, pi_I y and pi_F y), restart message mode, alpha = 0.75, at
-most 8 iterations with syndrome stopping, FP32; 1,000,000 frames per Eb/N0
-point, Eb/N0 = 1.0, 1.5, ..., 6.0 dB; random information bits, BPSK over
-AWGN, LLR = 2y/sigma^2 (seeded synthetic frames, resident in HBM before the
-timed region).  Each code's 11 points go through one decode call (22,000,000
-frames per step in two calls); --launch point makes every point a call of its
-own.
+Default workload "fix127" (one "step" = one pass of the whole decode path
+over the batch, in both precisions): BCH(127,64) with the optimised 72 x 127
+H_o and BCH(127,99) with the optimised 33 x 127 H_o; enhanced NMS with the
+9-branch automorphism block (three random cyclic shifts of y, pi_I y and
+pi_F y), restart message mode, at most 8 iterations with syndrome stopping,
+FP32 (alpha = 0.75) and int8 fixed point (alpha = 3/4 as a shift-add, LLRs
+quantised with scale 4); 4,000,000 frames per Eb/N0 point, Eb/N0 = 2.0, 2.5,
+..., 5.0 dB; random information bits, BPSK over AWGN, LLR = 2y/sigma^2 (seeded
+synthetic frames, resident in HBM before the timed region).  Each code's 7
+points go through one decode call per precision (56,000,000 frames per
+precision and step in four calls); --launch point makes every point a call
+of its own.
 
-Other workloads (--workload): "fix127", BCH(127,64) and BCH(127,99) at
-2.0..5.0 dB, 4,000,000 frames per point, FP32 and int8 fixed point; "mixed",
-16,000,000 frames of BCH(127,64)/(127,99)/(63,36) interleaved per frame
-(50/25/25 %) at Eb/N0 drawn per frame from U[1.5, 5] dB, decoded in one
-mixed-code call, FP32 and int8; "serve", the continuous-batching service
-with OSD-2; "latency", decode-call latency against the call size; "alpha",
-"ablation" and "beta", experiments of the method.
+Other workloads (--workload): "sweep63", BCH(63,45) and BCH(63,36) at
+1.0..6.0 dB, 1,000,000 frames per point, FP32; "mixed", 16,000,000 frames of
+BCH(127,64)/(127,99)/(63,36) interleaved per frame (50/25/25 %) at Eb/N0
+drawn per frame from U[1.5, 5] dB, decoded in one mixed-code call, FP32 and
+int8; "serve", the continuous-batching service with OSD-2; "latency",
+decode-call latency against the call size; "alpha", "ablation" and "beta",
+experiments of the method.
 
 Prints one JSON line with frames/s (value), information Gbit/s, per-launch
-p50/p99 latency, the VALU roofline of the decode kernel and the CPU oracle
-timed on a bounded sample of the same frames.
+p50/p99 latency, the VALU roofline of the dominant decode kernel (and per
+precision), and the CPU oracle decoding distinct frames of every Eb/N0 point
+within a time budget: its frame error rate beside the GPU's on the same
+frames (Wilson 95% intervals) and its throughput on the host's cores.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
 from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -67,27 +73,42 @@ WORKLOADS = {
 FIX_SCALE = 4.0
 
 # HBM traffic of the specialised decode kernels, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs of the default sweep (one call of 11,000,000 frames per code),
-# each scaled by what the same counter reads for a plain 1 GiB device copy
-# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  It holds only for the kernel sources the counters were taken on
-# (hash of the grouped kernel template, its rotation and frame hand-out
-# helpers, the launch header and the row-function generator); any other build
+# WRITE_SIZE runs, each scaled by what the same counter reads for a plain 1 GiB
+# device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0): bytes per frame of one
+# decode call of 28,000,000 frames (one code's seven Eb/N0 points of the
+# default workload).  An entry holds only for the kernel
+# sources the counters were taken on (a hash of the kernel family's templates
+# and of the generator functions that write its row function); any other build
 # reports traffic null.
-TRAFFIC_SRC_HASH = "ad8f123bafebf13c"
-TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written) bytes per frame
-    "spec_bch63_36_m122_b9": (300.21, 73.55),
-    "spec_bch63_45_m33_b9": (265.20, 68.51),
+TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written, family, source hash)
+    "spec_bch127_64_m72_b9": (522.72, 87.02, "one_wave", "88a5df35fd8d7ebd"),
+    "spec_bch127_99_m33_b9": (521.95, 88.21, "one_wave", "88a5df35fd8d7ebd"),
+    "spec_bch127_64_m72_b9_fix8_pk16": (135.85, 82.50, "pk16", "0ce47e9984fbfdc1"),
+    "spec_bch127_99_m33_b9_fix8_pk16": (135.48, 83.81, "pk16", "0ce47e9984fbfdc1"),
+}
+KERNEL_FAMILIES = {
+    "one_wave": (["csrc/nms_spec_fp32.inc", "csrc/nms_spec_rot.inc", "csrc/nms_spec_cursor.inc"],
+                 ["body_source_ilp", "syndrome_source", "_sign_masks", "_parity", "_MED3U"]),
+    "pk16": (["csrc/nms_spec_pk16.inc", "csrc/nms_spec_rot.inc", "csrc/nms_spec_cursor.inc"],
+             ["body_source_pk16", "syndrome_source", "_parity"]),
 }
 
 
-def kernel_src_hash():
+def kernel_src_hash(family):
+    """Hash of the files and generator functions behind a kernel family."""
     import hashlib
+    import inspect
+    from paper_2412_20828_amd import gen_spec
     pkg = os.path.join(ROOT, "paper_2412_20828_amd")
+    files, funcs = KERNEL_FAMILIES[family]
     outer = hashlib.sha256()
-    for f in ("csrc/nms_spec_group.inc", "csrc/nms_spec_rot.inc", "csrc/nms_spec_cursor.inc", "csrc/spec_launch.h",
-              "gen_spec.py"):
+    for f in files:
         with open(os.path.join(pkg, f), "rb") as fh:
             outer.update(hashlib.sha256(fh.read()).digest())
+    for name in funcs:
+        obj = getattr(gen_spec, name)
+        text = obj if isinstance(obj, str) else inspect.getsource(obj)
+        outer.update(hashlib.sha256(text.encode()).digest())
     return outer.hexdigest()[:16]
 
 
@@ -145,6 +166,36 @@ def pack(bits):
     return np.packbits(padded, axis=1, bitorder="little").view(np.uint64)
 
 
+# frames per Eb/N0 point kept on the host for the CPU oracle leg
+KEEP = 65536
+
+
+@dataclass
+class Sample:
+    """The first frames of one Eb/N0 point (or one code of a mixed call) with
+    the GPU's outcomes on them, for the oracle decoding the same frames."""
+    code: str
+    prec: str
+    ebn0: object
+    x: np.ndarray       # [n][ld] float32 LLRs or int8 quantised LLRs
+    d_o: np.ndarray
+    words: np.ndarray   # [n][W] uint64 GPU decisions
+    iters: np.ndarray
+    flags: np.ndarray
+    cw: np.ndarray      # [n][2] uint64 transmitted codewords
+
+
+def wilson(k, n, z=1.96):
+    """Wilson score interval of a binomial proportion k / n (95% for z = 1.96)."""
+    if n == 0:
+        return [0.0, 1.0]
+    p = k / n
+    den = 1.0 + z * z / n
+    c = (p + z * z / (2 * n)) / den
+    h = z * math.sqrt(p * (1 - p) / n + z * z / (4.0 * n * n)) / den
+    return [max(0.0, c - h), min(1.0, c + h)]
+
+
 class Item:
     """One launch of the timed step: a single-code decode or a mixed-code one."""
 
@@ -194,11 +245,24 @@ def make_decoder(args, B, code, pcm, name, rows, prec):
     autotuner's cached layout and grid (--tuned)."""
     precision = B.FIX8 if prec == "fix8" else B.FP32
     flags = (B.FORCE_GENERIC if args.generic else 0) | (B.PACKED16 if args.packed16 and prec == "fix8" else 0)
+    if getattr(args, "mixed_path", "fused") == "per-code":
+        flags |= B.NO_MIXED_KERNEL
+    alpha = workload_alpha(args, name, rows)
     if args.tuned and not args.generic:
         from paper_2412_20828_amd import autotune
-        return autotune.tuned_decoder(code, pcm, name, rows, precision=precision, flags=flags)
-    return B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8,
+        return autotune.tuned_decoder(code, pcm, name, rows, alpha=alpha, precision=precision, flags=flags)
+    return B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=alpha, max_iter=8,
                      precision=precision, flags=flags)
+
+
+def workload_alpha(args, name, rows):
+    """alpha of a code's FP32 decoder: --alpha as a number, or "tuned" (the
+    autotuner's cached argmin of the frame error rate, 0.75 when nothing is
+    cached).  The fixed-point decoders have alpha = 3/4 built in."""
+    if args.alpha == "tuned":
+        from paper_2412_20828_amd import autotune
+        return autotune.tuned_alpha(name, rows)
+    return float(args.alpha)
 
 
 def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_base):
@@ -219,13 +283,13 @@ def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_ba
             ld = 64 if code.N <= 64 else 128
             llr_d = torch.empty((F, ld), dtype=torch.float32, device=dev)
             d_o_d = torch.empty(F, dtype=torch.uint8, device=dev)
-            pts = []  # (Eb/N0, first frame, packed codewords, first 64 LLR rows, their d_o)
+            pts = []  # (Eb/N0, first frame, packed codewords, first KEEP LLR rows, their d_o)
             for j, pi in enumerate(grp):
                 llr, cw, d_o = gen_point(name, args.frames, points[pi], seed=seed_base + 10 * ci + pi)
                 f0 = j * args.frames
                 llr_d[f0:f0 + args.frames].copy_(torch.from_numpy(llr))
                 d_o_d[f0:f0 + args.frames].copy_(torch.from_numpy(d_o))
-                pts.append((points[pi], f0, pack(cw), llr[:64].copy(), d_o[:64].copy()))
+                pts.append((points[pi], f0, pack(cw), llr[:KEEP].copy(), d_o[:KEEP].copy()))
                 del llr, cw, d_o
             for prec in precisions:
                 dec = decs[prec]
@@ -262,11 +326,16 @@ def build_single(args, B, torch, dev, stream, codes, points, precisions, seed_ba
                     ops = I.sum() * alg_ops_per_iteration(code.N, code.K, pcm.M, pcm.E, 9)
                     return out, float(ops), len(I) * code.K
 
-                def sample(name=name, bits=bits, it=it, pts=pts):
+                def sample(name=name, prec=prec, bits=bits, it=it, fl=fl, pts=pts, inp=inp):
                     W = bits.cpu().numpy().view(np.uint64)
-                    I = it.cpu().numpy()
-                    return [(name, l64, d64, W[f0:f0 + 64], I[f0:f0 + 64]) for _, f0, _, l64, d64 in pts]
-                item.stats, item.sample = stats, (sample if prec == "fp32" else None)
+                    I, C = it.cpu().numpy(), fl.cpu().numpy()
+                    out = []
+                    for e, f0, cwp, lk, dk in pts:
+                        n = lk.shape[0]
+                        x = lk if prec == "fp32" else inp[f0:f0 + n].cpu().numpy()
+                        out.append(Sample(name, prec, e, x, dk, W[f0:f0 + n], I[f0:f0 + n], C[f0:f0 + n], cwp[:n]))
+                    return out
+                item.stats, item.sample = stats, sample
                 items.append(item)
             del llr_d
     return items, mats
@@ -306,6 +375,8 @@ def build_mixed(args, B, torch, dev, stream, codes, probs, lohi, precisions, see
         ws = torch.empty(max(1, mix.workspace_size(F)), dtype=torch.uint8, device=dev)
         item = Item("mixed", prec, F, lambda st=stream, mix=mix, inp=inp, bits=bits, it=it, fl=fl, ws=ws:
                     mix.decode_into(ci_d, inp, d_o_d, bits, it, fl, ws, stream=st))
+        # the mixed-code kernel's name, or per-code launches of this precision
+        item.kernel = mix.kernel_name if mix.kernel_name != "per-code" else "per-code_%s" % prec
 
         def stats(prec=prec, bits=bits, it=it, fl=fl):
             w = bits.cpu().numpy().view(np.uint64)
@@ -322,14 +393,16 @@ def build_mixed(args, B, torch, dev, stream, codes, probs, lohi, precisions, see
                 info += int(sel.sum()) * code.K
             return pts, float(ops), info
 
-        def sample(bits=bits, it=it):
+        def sample(prec=prec, bits=bits, it=it, fl=fl, inp=inp):
             out = []
+            W, I, C = bits.cpu().numpy().view(np.uint64), it.cpu().numpy(), fl.cpu().numpy()
             for k, (name, _) in enumerate(codes):
-                sel = np.nonzero(ci == k)[0][:64]
-                out.append((name, llr[sel].copy(), d_o[sel].copy(), bits.cpu().numpy().view(np.uint64)[sel],
-                            it.cpu().numpy()[sel]))
+                sel = np.nonzero(ci == k)[0][:KEEP]
+                x = llr[sel].copy() if prec == "fp32" else inp[torch.from_numpy(sel).to(dev)].cpu().numpy()
+                out.append(Sample(name, prec, "U[%g,%g]" % tuple(lohi), x, d_o[sel].copy(), W[sel], I[sel], C[sel],
+                                  cwp[sel]))
             return out
-        item.stats, item.sample = stats, (sample if prec == "fp32" else None)
+        item.stats, item.sample = stats, sample
         items.append(item)
     return items, mats
 
@@ -487,15 +560,17 @@ def run_latency(args):
 def run_experiment(args):
     """Experiments of the method on the GPU kernels.
 
-    alpha: frame error rate against the normalisation factor alpha (eq. 3) at
-    the Eb/N0 where the paper fixes it (2.6 dB for N = 63, 3.0 dB for N = 127),
-    9 branches, restart mode, I_m = 8, 10^6 frames per point; the argmin
-    stands in for the paper's trained, unprinted values.
+    alpha: the autotuner's alpha search (frame error rate against the
+    normalisation factor of eq. 3 at the Eb/N0 where the paper fixes it, 2.6 dB
+    for N = 63 and 3.0 dB for N = 127, 9 branches, restart mode, I_m = 8, 10^6
+    frames); the argmin stands in for the paper's trained, unprinted values.
 
     beta: the redundancy factor of H_o (step 5 of Section III-A): rows, edges,
-    length-4 cycles, FER and frames/s for beta in {1, 2, 4, 8, 20} for (63,36)
-    at 3 dB and {1, 2, 3} for (127,78) at 4 dB (matrices without a specialised
-    kernel run on the generic one, which the row marks).
+    length-4 cycles, FER, frames/s and VALU fraction for (63,36) at the
+    paper's (beta, M_o) list (1, 27), (5, 47), (20, 122), (50, 269), (60, 316)
+    at 3.5 dB with I_m = 4 and alpha tuned at 2.6 dB, and for (127,78) at
+    beta = 1, 2, 3 (49, 57, 65 rows) at 4 dB; every matrix has a specialised
+    kernel.
 
     ablation: what the automorphism merge buys: plain flooding NMS on the
     standard H (one branch, extrinsic messages), NMS on H_o (one branch,
@@ -510,47 +585,52 @@ def run_experiment(args):
            "data": "synthetic", "higher_is_better": True, "vs_baseline": None, "steps": 1, "warmup": 1}
     rows = []
     if args.workload == "alpha":
-        alphas = [round(0.5 + 0.05 * k, 2) for k in range(11)]
-        for ci, (name, rows_h, ebn0) in enumerate([("bch63_45", 33, 2.6), ("bch63_36", 122, 2.6),
-                                                   ("bch127_64", 72, 3.0), ("bch127_99", 33, 3.0)]):
+        from paper_2412_20828_amd import autotune
+        for ci, (name, rows_h) in enumerate([("bch63_45", 33), ("bch63_36", 122), ("bch127_64", 72),
+                                             ("bch127_99", 33)]):
             d = B.CODE_DEFS[name]
             code = B.Code(d.m, d.prim, d.t)
             pcm = B.Pcm.build(code, target_rows=rows_h, seed=1)
-            llr_h, cw, d_o_h = gen_point(name, F, ebn0, seed=6000 + ci)
-            truth = pack(cw)
-            llr, d_o = torch.from_numpy(llr_h).to(dev), torch.from_numpy(d_o_h).to(dev)
-            fers = []
-            for a in alphas:
-                dec = B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=a, max_iter=8)
-                w, it, fl, sec = timed_decode(dec, llr, d_o, torch, reps=1)
-                fer = float((w != truth[:, :w.shape[1]]).any(1).mean())
-                fers.append(fer)
-                rows.append({"code": name, "rows": rows_h, "ebn0": ebn0, "alpha": a, "fer": fer,
-                             "avg_iters": float(it.mean()), "frames_per_s": F / sec})
-            best = alphas[int(np.argmin(fers))]
-            rows.append({"code": name, "best_alpha": best, "fer_at_best": min(fers),
-                         "fer_at_0.75": fers[alphas.index(0.75)]})
-        out.update({"workload": "alpha", "config": {"workload": "alpha sweep 0.50:0.05:1.00, 9 branches, restart "
-                                                               "mode, I_m 8, %d frames per point" % F}})
+            e = autotune.search_alpha(code, pcm, name, rows_h, frames=F, seed=6000 + ci, write=args.write_alpha)
+            rows.append({"code": name, "rows": rows_h, **e, "cached": args.write_alpha})
+        out.update({"workload": "alpha", "config": {"workload": "alpha search: FER of the FP32 9-branch restart-"
+                                                               "mode decoder, I_m 8, %d frames, grid 0.50:0.05:1.10 "
+                                                               "widened until the argmin is inside" % F}})
     elif args.workload == "beta":
-        # H_o redundancy: M_o = M_r1 + beta (M - M_r1) rows (step 5 of Section III-A)
-        for ci, (name, betas, ebn0) in enumerate([("bch63_36", [1, 2, 4, 8, 20], 3.0),
-                                                  ("bch127_78", [1, 2, 3], 4.0)]):
+        # the redundancy list of Section III-A: (63,36) at beta = 1, 5, 20, 50, 60
+        # with the row counts the paper prints (27, 47, 122, 269, 316), FER at
+        # 3.5 dB with I_m = 4 and alpha tuned at 2.6 dB; (127,78) at beta = 1, 2, 3
+        # (49, 57, 65 rows: M_o = M_r1 + beta (M - M_r1) with Table 1's
+        # M_r1 = 41) at 4 dB with I_m = 8
+        from paper_2412_20828_amd import autotune
+        for ci, (name, betas, ebn0, im, tune_rows) in enumerate([
+                ("bch63_36", [(1, 27), (5, 47), (20, 122), (50, 269), (60, 316)], 3.5, 4, 122),
+                ("bch127_78", [(1, 49), (2, 57), (3, 65)], 4.0, 8, 57)]):
             d = B.CODE_DEFS[name]
             code = B.Code(d.m, d.prim, d.t)
+            ref = B.Pcm.build(code, target_rows=tune_rows, seed=1)
+            alpha = autotune.tuned_alpha(name, tune_rows, max_iter=im, default=float("nan"))
+            if alpha != alpha:
+                alpha = autotune.search_alpha(code, ref, name, tune_rows, frames=F, max_iter=im,
+                                              seed=8100 + ci, write=args.write_alpha)["alpha"]
             llr_h, cw, d_o_h = gen_point(name, F, ebn0, seed=8000 + ci)
             truth = pack(cw)
             llr, d_o = torch.from_numpy(llr_h).to(dev), torch.from_numpy(d_o_h).to(dev)
-            for beta in betas:
-                pcm = B.Pcm.build(code, beta=beta, seed=1)
-                dec = B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8)
-                w, it, fl, sec = timed_decode(dec, llr, d_o, torch, reps=1)
+            for beta, mo in betas:
+                pcm = B.Pcm.build(code, target_rows=mo, seed=1)
+                dec = B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=alpha, max_iter=im)
+                w, it, fl, sec = timed_decode(dec, llr, d_o, torch, reps=2)
+                st = pcm.stats()
+                ops = float(it.astype(np.int64).sum()) * alg_ops_per_iteration(code.N, code.K, pcm.M, pcm.E, 9)
                 rows.append({"code": name, "beta": beta, "rows": pcm.M, "edges": pcm.E, "four_cycles": pcm.c4,
-                             "ebn0": ebn0, "fer": float((w != truth[:, :w.shape[1]]).any(1).mean()),
+                             "row_weights": st["row_range"], "col_weights": st["col_range"],
+                             "ebn0": ebn0, "max_iter": im, "alpha": alpha,
+                             "fer": float((w != truth[:, :w.shape[1]]).any(1).mean()),
                              "avg_iters": float(it.mean()), "frames_per_s": F / sec,
-                             "specialised_kernel": dec.specialized})
+                             "valu_frac": ops / sec / VALU_PEAK_OPS,
+                             "kernel": dec.kernel_name(F) if dec.specialized else "generic"})
         out.update({"workload": "beta", "config": {"workload": "H_o redundancy sweep, 9 branches, restart mode, "
-                                                              "alpha 0.75, I_m 8, %d frames per point" % F}})
+                                                              "%d frames per point" % F}})
     else:
         points = [2.0, 3.0, 4.0]
         for ci, (name, rows_h) in enumerate([("bch63_45", 33), ("bch63_36", 122)]):
@@ -654,12 +734,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sweep63", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="fix127", choices=sorted(WORKLOADS))
     ap.add_argument("--frames", type=int, default=0, help="frames per Eb/N0 point (0: the workload's)")
     ap.add_argument("--ebn0", type=str, default="", help="lo:hi:step dB (empty: the workload's)")
     ap.add_argument("--launch", default="code", choices=["code", "point"],
                     help="sweeps: one decode call per code over all its Eb/N0 points, or one per point")
-    ap.add_argument("--cpu-seconds", type=float, default=30.0, help="budget of the CPU oracle leg")
+    ap.add_argument("--cpu-seconds", type=float, default=30.0,
+                    help="budget of the CPU oracle leg (FP64; the integer oracle gets a third of it)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--generic", action="store_true", help="force the generic (unspecialised) kernel")
     ap.add_argument("--tuned", action="store_true",
@@ -667,8 +748,13 @@ def main():
     ap.add_argument("--precision", default="", choices=["", "fp32", "fix8", "both"],
                     help="override the workload's precisions")
     ap.add_argument("--packed16", action="store_true", help="fixed point: the packed 16-bit kernels (two frames per lane)")
+    ap.add_argument("--alpha", default="0.75",
+                    help='alpha of the FP32 decoders: a number, or "tuned" (the autotuner\'s cached search result)')
     ap.add_argument("--graph", action="store_true",
                     help="capture each launch of the step in a HIP graph once and replay it in the timed loop")
+    ap.add_argument("--write-alpha", action="store_true", help="alpha workload: cache the results in tuning.json")
+    ap.add_argument("--mixed-path", default="fused", choices=["fused", "per-code"],
+                    help="mixed workload: the mixed-code kernel (one launch) or one launch per code")
     ap.add_argument("--requests", type=int, default=3000, help="requests of the serving workload")
     ap.add_argument("--osd", default="device", choices=["device", "host"], help="serving: where OSD-2 runs")
     ap.add_argument("--slots", type=int, default=3, help="serving: batches in flight (slots)")
@@ -710,6 +796,9 @@ def main():
     if args.precision:
         precisions = ["fp32", "fix8"] if args.precision == "both" else [args.precision]
         wdesc = wdesc.split(", FP32")[0] + ", precision " + "+".join(precisions)
+    if args.alpha != "0.75" and "fp32" in precisions:
+        wdesc += "; FP32 alpha %s" % (", ".join("%s %.2f" % (n, workload_alpha(args, n, r)) for n, r in codes)
+                                      if args.alpha == "tuned" else args.alpha)
     args.frames = args.frames or frames
     args.ebn0 = args.ebn0 or grid
     dev = torch.device("cuda:0")
@@ -796,14 +885,28 @@ def main():
         g[2] += 1
         g[3] += item.frames
 
+    by_prec_kernel = {}
+    for k, item in enumerate(items):
+        g = by_prec_kernel.setdefault(item.prec, {}).setdefault(item.kernel, [0.0, 0.0, 0])
+        g[0] += launch_ms[:, k].sum() / 1e3 / args.steps
+    for kname, (t_k, ops_k, n_k, _) in by_kernel.items():
+        for prec in by_prec_kernel:
+            if kname in by_prec_kernel[prec]:
+                by_prec_kernel[prec][kname][1:] = [ops_k, n_k]
+    roof_prec = {}
+    for prec, ks in by_prec_kernel.items():
+        kd = max(ks, key=lambda n: ks[n][0])
+        t_k, ops_k, n_k = ks[kd]
+        roof_prec[prec] = {"kernel": kd, "achieved": ops_k / t_k / 1e12, "frac": ops_k / t_k / VALU_PEAK_OPS,
+                           "avg_launch_ms": t_k / n_k * 1e3, "algorithmic_ops_per_launch": ops_k / n_k}
     kernel_s = launch_ms.sum() / 1e3 / args.steps
     achieved_all = ops_total / kernel_s
     dom = max(by_kernel, key=lambda n: by_kernel[n][0])
     t_dom, ops_dom, n_dom, fr_dom = by_kernel[dom]
     achieved = ops_dom / t_dom
     traffic = None
-    if dom in TRAFFIC_B_PER_FRAME and kernel_src_hash() == TRAFFIC_SRC_HASH:
-        traffic = sum(TRAFFIC_B_PER_FRAME[dom]) * fr_dom / n_dom
+    if dom in TRAFFIC_B_PER_FRAME and kernel_src_hash(TRAFFIC_B_PER_FRAME[dom][2]) == TRAFFIC_B_PER_FRAME[dom][3]:
+        traffic = sum(TRAFFIC_B_PER_FRAME[dom][:2]) * fr_dom / n_dom
     frames_per_s = total_frames * args.steps / elapsed
     res = {
         "metric": "decoded frames/s & info Gbit/s at matched FER vs oracle; p50/p99 latency",
@@ -834,10 +937,11 @@ def main():
                      "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
                      "kernel": dom, "launches_per_step": n_dom, "avg_launch_ms": t_dom / n_dom * 1e3,
                      "algorithmic_ops_per_launch": ops_dom / n_dom,
-                     "traffic_bytes_per_frame": (list(TRAFFIC_B_PER_FRAME[dom]) if traffic else None),
+                     "traffic_bytes_per_frame": (list(TRAFFIC_B_PER_FRAME[dom][:2]) if traffic else None),
                      "hbm": ({"achieved_gb_s": traffic / (t_dom / n_dom) / 1e9, "peak_gb_s": HBM_PEAK_BYTES / 1e9,
                               "frac": traffic / (t_dom / n_dom) / HBM_PEAK_BYTES} if traffic else None),
                      "all_kernels": {"achieved": achieved_all / 1e12, "frac": achieved_all / VALU_PEAK_OPS}},
+        "roofline_by_precision": roof_prec,
         "points": per_point,
         "input_generation_s": gen_s,
     }
@@ -848,7 +952,7 @@ def main():
         res["fix8_fer_loss"] = [{"code": c, "ebn0": e, "fer_fp32": fer[(c, e, "fp32")], "fer_fix8": fer[(c, e, "fix8")]}
                                 for (c, e, p) in fer if p == "fp32"]
     if not args.no_cpu:
-        samples = [s for it in items if it.sample is not None for s in it.sample()]
+        samples = [s for it in items for s in it.sample()]
         res["cpu_baseline"] = cpu_baseline(samples, mats, args.cpu_seconds, frames_per_s)
     print(json.dumps(res))
 
@@ -864,50 +968,78 @@ def oracle_matrices(oracle, name, pcm):
     return H, oc.Hstd
 
 
+def _oracle_pass(oracle, Hs, samples, n_of, threads, kind):
+    """Decode the first n_of[k] frames of every sample k with the oracle;
+    returns (seconds, frames, per-sample results)."""
+    t0 = time.time()
+    out = []
+    frames = 0
+    for k, sm in enumerate(samples):
+        H, Hstd = Hs[sm.code]
+        n = n_of[k]
+        c, it, cv = oracle.decode_batch(H, Hstd, sm.x[:n], sm.d_o[:n], 9, 0.75, 8, oracle.R1, kind=kind,
+                                        threads=threads)
+        out.append((c, it, cv))
+        frames += n
+    return time.time() - t0, frames, out
+
+
 def cpu_baseline(samples, mats, budget_s, gpu_fps):
-    """The FP64 oracle (as it stands) on a bounded sample of the same frames,
-    on all host cores; also checks that the GPU outcomes on that sample are
-    the oracle's (matched FER)."""
+    """The oracle as it stands, on distinct frames of every Eb/N0 point (the
+    first frames of each point, as many as fit the budget) on all host cores:
+    the FP64 oracle on the FP32 points (its throughput is the reported
+    value), the integer oracle on the fixed-point points (a third of the
+    budget).  Per point it puts the oracle's frame error rate beside the
+    GPU's on the same frames, each with a Wilson 95% interval, and counts the
+    frames whose GPU word, iteration count and flag equal the oracle's."""
     import oracle
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    Hs = {}
-    for name in mats:
-        Hs[name] = oracle_matrices(oracle, name, mats[name])
-    # pilot (every sample once) to size the repeat count to the budget
-    t0 = time.time()
-    for name, l0, d0, _, _ in samples:
-        oracle.decode_batch(Hs[name][0], Hs[name][1], l0, d0, 9, 0.75, 8, oracle.R1, threads=threads)
-    pilot = max(time.time() - t0, 1e-3)
-    reps = max(1, int(budget_s / pilot))
-    n = match = total = 0
-    t0 = time.time()
-    for name, l, d, gw, gi in samples:
-        H, Hstd = Hs[name]
-        per = l.shape[0]
-        c, it, cv = oracle.decode_batch(H, Hstd, np.tile(l, (reps, 1)), np.tile(d, reps), 9, 0.75, 8, oracle.R1,
-                                        threads=threads)
-        n += per * reps
-        W = (H.shape[1] + 63) // 64
-        ow = pack(c[:per])[:, :W]
-        match += int(((gw[:, :W] == ow).all(1) & (gi == it[:per])).sum())
-        total += per
-    secs = time.time() - t0
-    # one core: the first sample only, repeated for about a tenth of the budget
-    name, l, d, _, _ = samples[0]
-    H, Hstd = Hs[name]
+    Hs = {name: oracle_matrices(oracle, name, mats[name]) for name in mats}
+    legs = {"fp32": (oracle.KIND_FAST, budget_s), "fix8": (oracle.KIND_FIXED, budget_s / 3.0)}
+    report, paired = {}, []
+    for prec, (kind, budget) in legs.items():
+        sm = [x for x in samples if x.prec == prec]
+        if not sm:
+            continue
+        pilot_n = [min(256, x.x.shape[0]) for x in sm]
+        secs, frames, _ = _oracle_pass(oracle, Hs, sm, pilot_n, threads, kind)
+        rate = frames / max(secs, 1e-3)
+        per = max(256, int(budget * rate / len(sm)))
+        n_of = [min(per, x.x.shape[0]) for x in sm]
+        secs, frames, res = _oracle_pass(oracle, Hs, sm, n_of, threads, kind)
+        match = 0
+        for x, n, (c, it, cv) in zip(sm, n_of, res):
+            W = (Hs[x.code][0].shape[1] + 63) // 64
+            ow = pack(c)[:, :W]
+            gw = x.words[:n, :W]
+            cw = x.cw[:n, :W]
+            same = (gw == ow).all(1) & (x.iters[:n] == it) & (x.flags[:n].astype(bool) == cv)
+            match += int(same.sum())
+            eo = int((ow != cw).any(1).sum())
+            eg = int((gw != cw).any(1).sum())
+            paired.append({"code": x.code, "precision": prec, "ebn0": x.ebn0, "frames": n,
+                           "oracle_fer": eo / n, "oracle_ci95": wilson(eo, n),
+                           "gpu_fer": eg / n, "gpu_ci95": wilson(eg, n), "identical": int(same.sum())})
+        report[prec] = {"frames_per_s": frames / secs, "frames": frames, "seconds": secs, "frames_per_point": per,
+                        "identical_fraction": match / max(1, frames)}
+    fp = report.get("fp32") or next(iter(report.values()))
+    # one core: the first FP32 sample, for about a tenth of the budget
+    x = next(v for v in samples if v.prec == "fp32") if any(v.prec == "fp32" for v in samples) else samples[0]
+    H, Hstd = Hs[x.code]
+    kind = oracle.KIND_FAST if x.prec == "fp32" else oracle.KIND_FIXED
     t1 = time.time()
     n1 = 0
     while time.time() - t1 < budget_s / 10:
-        oracle.decode_batch(H, Hstd, l, d, 9, 0.75, 8, oracle.R1, threads=1)
-        n1 += l.shape[0]
+        oracle.decode_batch(H, Hstd, x.x[:256], x.d_o[:256], 9, 0.75, 8, oracle.R1, kind=kind, threads=1)
+        n1 += min(256, x.x.shape[0])
     one = n1 / (time.time() - t1)
-    return {"value": n / secs, "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": "%d frames (the first 64 frames of each of %d slices: an Eb/N0 point of a code, or "
-                      "a code of the mixed call; %d repeats), FP64 "
-                      "min1/min2 oracle, same frames as the GPU" % (n, len(samples), reps),
-            "seconds": secs, "gpu_over_cpu": gpu_fps / (n / secs),
-            "one_core": {"value": one, "sample": "%d frames of %s" % (n1, name)},
-            "oracle_match_fraction": match / max(1, total)}
+    return {"value": fp["frames_per_s"], "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": "%d distinct frames: the first %d frames of each of %d Eb/N0 points (or codes of a mixed "
+                      "call), FP64 min1/min2 oracle on the same FP32 LLRs as the GPU" % (
+                          fp["frames"], fp["frames_per_point"], sum(1 for v in samples if v.prec == "fp32")),
+            "seconds": fp["seconds"], "gpu_over_cpu": gpu_fps / fp["frames_per_s"],
+            "one_core": {"value": one, "sample": "%d frames of %s at %s dB" % (n1, x.code, x.ebn0)},
+            "by_precision": report, "fer_paired": paired}
 
 
 if __name__ == "__main__":

@@ -145,16 +145,22 @@ enum { BCH_MODE_RESTART = 1, BCH_MODE_MEMORY = 2, BCH_MODE_EXTRINSIC = 3 };
 enum { BCH_FP32 = 0, BCH_FIX8 = 1 };
 enum {
     BCH_DEC_FORCE_GENERIC = 1, /* do not use a PCM-specialised kernel */
-    BCH_DEC_PACKED16 = 2,      /* BCH_FIX8: the packed 16-bit kernel (two frames per lane,
-                                  same results), registered for the four workload matrices of
-                                  N = 63 and 127; without it the fixed-point kernel holds its
-                                  integers in 32-bit registers */
+    BCH_DEC_PACKED16 = 2,      /* BCH_FIX8: always the packed 16-bit kernel (two frames per
+                                  lane, same results), registered for the four workload
+                                  matrices of N = 63 and 127.  Without this flag a fixed-point
+                                  decode of at least 4,000,000 frames (N = 127) or 8,000,000
+                                  (N = 63) runs it where registered, a smaller one the kernel
+                                  that holds its integers in 32-bit registers */
     BCH_DEC_SMALL_ALWAYS = 4,  /* N = 127: always use the small-batch kernel (the nine
                                   branches of 64 frames on three waves) where registered */
-    BCH_DEC_SMALL_NEVER = 8    /* N = 127: never use it.  Without either flag a decode of at
+    BCH_DEC_SMALL_NEVER = 8,   /* N = 127: never use it.  Without either flag a decode of at
                                   most 128 frames per CU uses it, a larger one the kernel
                                   of one wave per 64 frames; the results are the same.
                                   Both flags together, or any other bit, give BCH_EINVAL */
+    BCH_DEC_UNPACKED16 = 16,   /* BCH_FIX8: never the packed 16-bit kernel (with
+                                  BCH_DEC_PACKED16: BCH_EINVAL) */
+    BCH_DEC_NO_MIXED_KERNEL = 32 /* a mixed-code call that includes this decoder runs one
+                                  prepass and kernel per code (bch_mixed_decode_batch) */
 };
 typedef struct {
     int n_branches; /* 1, 3 or 9 */
@@ -228,10 +234,15 @@ int bch_decoder_set_tuning(bch_decoder dec, int waves_per_cu);
  * n_codes are left untouched).  Every decoder needs a specialised kernel and
  * all share the precision.  llr: device [F][ld] with ld >= every N; bits:
  * device [F][bits_ld] uint64, bits_ld >= every ceil(N/64); iters, flags: as
- * bch_nms_decode_batch; F <= BCH_MAX_FRAMES.  One prepass and one persistent
- * kernel per code are enqueued on stream (no host synchronisation, no memset:
- * the call can be captured in a HIP graph and replayed).  Per-frame results do
- * not depend on the mix: each frame decodes exactly as alone.
+ * bch_nms_decode_batch; F <= BCH_MAX_FRAMES.  When the library carries a
+ * mixed-code kernel for these decoders' matrices in this order (nine-branch,
+ * restart-mode decoders of one precision, none with BCH_DEC_NO_MIXED_KERNEL),
+ * the call enqueues one prepass that buckets every frame by (code, d_o) and
+ * one persistent kernel whose waves take frames of any code (the batching
+ * pattern of one launch for a mixed batch); otherwise one prepass and one
+ * persistent kernel per code.  No host synchronisation, no memset: the call
+ * can be captured in a HIP graph and replayed.  Per-frame results do not
+ * depend on the mix or the path: each frame decodes exactly as alone.
  */
 #define BCH_MAX_MIX 8
 size_t bch_mixed_workspace_size(const bch_decoder *decs, int n_codes, int64_t F);
@@ -239,6 +250,11 @@ int bch_mixed_decode_batch(const bch_decoder *decs, int n_codes, const uint8_t *
                            int64_t ld, int64_t F, const uint8_t *d_o, uint64_t *bits, int64_t bits_ld,
                            uint8_t *iters, uint8_t *flags, void *workspace, size_t ws_bytes,
                            hipStream_t stream);
+
+/* Name of the kernel a mixed call over decs[0..n_codes) runs: the mixed-code
+ * kernel's, or "per-code" ("" for bad arguments); static, owned by the
+ * library. */
+const char *bch_mixed_kernel_name(const bch_decoder *decs, int n_codes);
 
 /* Syndrome test of eq. 5 with the code's standard PCM: ok[f] = 1 iff
  * H c_f^T = 0.  bits: device [F][ceil(N/64)] uint64; ok: device [F] uint8. */

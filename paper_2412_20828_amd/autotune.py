@@ -1,6 +1,15 @@
-"""Autotuner of the specialised decoders' launch shape.
+"""Autotuner of the specialised decoders: launch shape and normalisation factor.
 
-Knobs:
+The normalisation factor alpha of eq. 3 is the one scalar the method tunes;
+the paper trains it as a network weight at one Eb/N0 per block length (2.6 dB
+for N = 63, 3.0 dB for N = 127) and fixes it, without printing the values.
+search_alpha() stands in for that training: the frame error rate of the FP32
+nine-branch decoder on one synthetic batch at that Eb/N0 for every alpha of a
+grid, the grid widened by 0.05 steps until the least error rate is inside it,
+and the argmin cached per (code, rows of H_o, I_m); tuned_alpha() returns it
+(0.75 when nothing is cached).
+
+Launch-shape knobs:
   - frames per wave of the fixed-point decoders: 64 (integers held in 32-bit
     registers) or 128 (the packed 16-bit kernels, two frames per lane);
   - waves per CU of the persistent grid.
@@ -59,13 +68,85 @@ def tuned_decoder(code, pcm, code_name: str, rows: int, n_branches=9, mode=None,
     from . import binding as B
     mode = B.MODE_RESTART if mode is None else mode
     entry = load().get(key(code_name, rows, precision, n_branches, _gpu_name()))
-    if entry and entry.get("packed16"):
-        flags |= B.PACKED16
+    if entry and precision == B.FIX8:
+        flags |= B.PACKED16 if entry.get("packed16") else B.UNPACKED16
     dec = B.Decoder(code, pcm, n_branches=n_branches, mode=mode, alpha=alpha, max_iter=max_iter,
                     precision=precision, flags=flags)
     if entry and dec.specialized:
         dec.set_tuning(entry["waves_per_cu"])
     return dec
+
+
+ALPHA_GRID = [round(0.5 + 0.05 * k, 2) for k in range(13)]  # 0.50 .. 1.10
+ALPHA_EBN0 = {63: 2.6, 127: 3.0}  # where the paper fixes alpha, per block length
+ALPHA_MAX = 2.0
+
+
+def alpha_key(code_name: str, rows: int, max_iter: int) -> str:
+    return "alpha/%s/m%d/i%d" % (code_name, rows, max_iter)
+
+
+def tuned_alpha(code_name: str, rows: int, max_iter: int = 8, default: float = 0.75) -> float:
+    """The cached alpha of a code's decoder, or default."""
+    entry = load().get(alpha_key(code_name, rows, max_iter))
+    return float(entry["alpha"]) if entry else default
+
+
+def search_alpha(code, pcm, code_name: str, rows: int, ebn0: float = None, frames: int = 1_000_000,
+                 max_iter: int = 8, seed: int = 6000, grid=None, write: bool = True):
+    """Frame error rate of the FP32 nine-branch restart-mode decoder for every
+    alpha of the grid on one batch at ebn0 (default: the paper's tuning
+    Eb/N0 of the block length); the grid grows by 0.05 at either end while
+    the least error rate sits on that end (up to ALPHA_MAX).  Returns the
+    entry {alpha, ebn0, frames, max_iter, fer: {alpha: FER}, bracketed}."""
+    import numpy as np
+    import torch
+
+    import synth
+    from . import binding as B
+    ebn0 = ALPHA_EBN0.get(code.N, 3.0) if ebn0 is None else ebn0
+    grid = sorted(grid or ALPHA_GRID)
+    ld = 64 if code.N <= 64 else 128
+    llr = torch.empty((frames, ld), dtype=torch.float32, device="cuda")
+    d_o = torch.empty(frames, dtype=torch.uint8, device="cuda")
+    cw = np.zeros((frames, code.N), np.uint8)
+    blk = 250_000
+    for k, f0 in enumerate(range(0, frames, blk)):
+        q = synth.frames(code_name, min(blk, frames - f0), ebn0, seed=seed, block=k)
+        llr[f0:f0 + len(q.d_o)].copy_(torch.from_numpy(q.llr))
+        d_o[f0:f0 + len(q.d_o)].copy_(torch.from_numpy(q.d_o))
+        cw[f0:f0 + len(q.d_o)] = q.codewords
+    padded = np.zeros((frames, 128), np.uint8)
+    padded[:, :code.N] = cw
+    truth = torch.from_numpy(np.packbits(padded, axis=1, bitorder="little").view(np.int64)).cuda()
+    fer = {}
+
+    def run(a):
+        dec = B.Decoder(code, pcm, n_branches=9, mode=B.MODE_RESTART, alpha=a, max_iter=max_iter)
+        bits, _, _, _ = dec.decode(llr, d_o)
+        fer[a] = float((bits != truth[:, :dec.W64]).any(1).float().mean())
+
+    for a in grid:
+        run(a)
+    while True:
+        best = min(fer, key=lambda a: (fer[a], abs(a - 0.75)))
+        lo, hi = min(fer), max(fer)
+        if best == hi and hi + 0.05 <= ALPHA_MAX + 1e-9:
+            run(round(hi + 0.05, 2))
+        elif best == lo and lo - 0.05 > 0.0:
+            run(round(lo - 0.05, 2))
+        else:
+            break
+    best = min(fer, key=lambda a: (fer[a], abs(a - 0.75)))
+    entry = {"alpha": best, "ebn0": ebn0, "frames": frames, "max_iter": max_iter,
+             "fer": {"%.2f" % a: fer[a] for a in sorted(fer)},
+             "bracketed": min(fer) < best < max(fer)}
+    if write:
+        cache = load()
+        cache[alpha_key(code_name, rows, max_iter)] = entry
+        with open(CACHE, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+    return entry
 
 
 def default_frames(N: int) -> int:
@@ -155,7 +236,7 @@ def tune_layout(code, pcm, code_name: str, rows: int, precision: int, ebn0: floa
     a nine-branch decoder; cache and return the best entry and every layout's
     (best entry, timings)."""
     from . import binding as B
-    cands = [0] + ([B.PACKED16] if precision == B.FIX8 else [])
+    cands = [B.UNPACKED16, B.PACKED16] if precision == B.FIX8 else [0]
     batch = None
     out = []
     for fl in cands:
@@ -187,9 +268,24 @@ def main():
     ap.add_argument("--frames", type=int, default=0,
                     help="frames per timed launch (0: 11 10^6 for N = 63, 4 10^6 for N = 127)")
     ap.add_argument("--out", default=CACHE, help="JSON cache to update")
+    ap.add_argument("--alpha", action="store_true",
+                    help="search alpha (FER argmin at the paper's tuning Eb/N0) instead of the launch shape")
+    ap.add_argument("--alpha-frames", type=int, default=1_000_000)
+    ap.add_argument("--max-iter", type=int, default=8, help="I_m of the alpha search")
     args = ap.parse_args()
     CACHE = args.out
     from . import binding as B
+    if args.alpha:
+        for spec in args.codes.split(","):
+            name, rows = spec.split(":")
+            d = B.CODE_DEFS[name]
+            code = B.Code(d.m, d.prim, d.t)
+            pcm = B.Pcm.build(code, target_rows=int(rows), seed=1)
+            e = search_alpha(code, pcm, name, int(rows), frames=args.alpha_frames, max_iter=args.max_iter)
+            print("%s/%s, I_m %d: alpha %.2f (FER %.5f at %.1f dB; 0.75: %.5f)" % (
+                name, rows, args.max_iter, e["alpha"], e["fer"]["%.2f" % e["alpha"]], e["ebn0"], e["fer"]["0.75"]),
+                flush=True)
+        return
     for spec in args.codes.split(","):
         name, rows = spec.split(":")
         rows = int(rows)

@@ -24,6 +24,8 @@ FORCE_GENERIC = 1
 PACKED16 = 2
 SMALL_ALWAYS = 4
 SMALL_NEVER = 8
+UNPACKED16 = 16
+NO_MIXED_KERNEL = 32
 
 SYMBOLS = [
     "bch_last_error", "bch_load_code", "bch_code_info", "bch_code_export", "bch_code_destroy",
@@ -33,7 +35,7 @@ SYMBOLS = [
     "bch_decoder_destroy", "bch_decode_workspace_size", "bch_nms_decode_batch",
     "bch_syndrome_check", "bch_quantize_llr", "bch_osd_decode", "bch_decoder_set_tuning",
     "bch_mixed_workspace_size", "bch_mixed_decode_batch", "bch_osd_decode_device", "bch_mixed_osd_decode",
-    "bch_draw_offsets", "bch_pcm_stats", "bch_nms_decode_batch_noalloc",
+    "bch_draw_offsets", "bch_pcm_stats", "bch_nms_decode_batch_noalloc", "bch_mixed_kernel_name",
 ]
 MAX_MIX = 8
 
@@ -101,6 +103,8 @@ def lib():
     L.bch_mixed_workspace_size.argtypes = [P, i32, i64]
     L.bch_mixed_workspace_size.restype = ctypes.c_size_t
     L.bch_mixed_decode_batch.argtypes = [P, i32, P, P, i64, i64, P, P, i64, P, P, P, ctypes.c_size_t, P]
+    L.bch_mixed_kernel_name.argtypes = [P, i32]
+    L.bch_mixed_kernel_name.restype = ctypes.c_char_p
     L.bch_osd_decode_device.argtypes = [P, P, i64, i64, i32, P, P, i64, P]
     L.bch_mixed_osd_decode.argtypes = [P, i32, P, P, i64, i64, i32, P, P, i64, P]
     _lib = L
@@ -310,8 +314,10 @@ class Decoder:
 
 
 class MixedDecoder:
-    """Frames of several codes interleaved in one batch (one prepass and one
-    persistent kernel per code, all enqueued on one stream)."""
+    """Frames of several codes interleaved in one batch: one code-keyed
+    prepass and one persistent kernel when the library has a mixed-code
+    kernel for these matrices, else one of each per code, all enqueued on one
+    stream."""
 
     def __init__(self, decoders):
         if not 1 <= len(decoders) <= MAX_MIX:
@@ -323,6 +329,11 @@ class MixedDecoder:
 
     def workspace_size(self, F: int) -> int:
         return int(lib().bch_mixed_workspace_size(self._arr, len(self.decoders), F))
+
+    @property
+    def kernel_name(self) -> str:
+        """The mixed-code kernel the call runs, or "per-code"."""
+        return lib().bch_mixed_kernel_name(self._arr, len(self.decoders)).decode()
 
     def decode_into(self, code_idx, llr, d_o, bits, iters, flags, workspace, stream=None):
         F, ld = llr.shape

@@ -55,10 +55,18 @@ def _compile_host(src, extra_inc=None):
     return out
 
 
+# The mixed-code kernels merge each permutation type into the accumulator in
+# one of three branches with fixed register indices; SimplifyCFG would sink
+# the three branches into one with dynamically indexed arrays, which then live
+# in scratch memory.
+MIXFLAGS = ["-mllvm", "-simplifycfg-sink-common=false"]
+
+
 def _compile_hip(src, extra_inc=None):
     out = _obj(src)
     inc = ["-I" + extra_inc] if extra_inc else []
-    _run([os.path.join(ROCM, "bin", "hipcc")] + HIPFLAGS + inc + ["-c", src, "-o", out])
+    extra = MIXFLAGS if os.path.basename(src).startswith("mix_") else []
+    _run([os.path.join(ROCM, "bin", "hipcc")] + HIPFLAGS + extra + inc + ["-c", src, "-o", out])
     return out
 
 
@@ -82,7 +90,8 @@ def build(verbose: bool = True, with_spec: bool = True) -> str:
     os.makedirs(gen_dir, exist_ok=True)
     # stage 1: empty specialisation table
     _write_if_changed(os.path.join(gen_dir, "spec_table.inc"),
-                      "static const SpecKernel kSpecKernels[] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n")
+                      "static const SpecKernel kSpecKernels[] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n"
+                      "static const MixKernel kMixKernels[] = {{0, {0}, 0, nullptr, nullptr}};\n")
     jobs = [(_compile_host, os.path.join(CSRC, s), gen_dir) for s in HOST_SRCS]
     with cf.ThreadPoolExecutor(max_workers=8) as ex:
         futs = [ex.submit(fn, src, inc) for fn, src, inc in jobs]

@@ -33,6 +33,8 @@ struct bch_decoder_s {
     int waves = 0;  // waves per CU of the persistent grid (0: the kernel's default)
     const bch::SpecKernel *spec = nullptr;        // throughput kernel
     const bch::SpecKernel *spec_small = nullptr;  // small-batch kernel (N = 127), or null
+    const bch::SpecKernel *spec_packed = nullptr; // fixed point: packed 16-bit kernel for large calls, or null
+    uint64_t fingerprint = 0;                     // of the matrix (mixed-code kernel lookup)
 };
 
 namespace bch {
@@ -100,6 +102,13 @@ static int waves_of(const bch_decoder_s *d)
     return d->waves > 0 ? d->waves : d->spec->waves_per_cu;
 }
 
+// fixed point: calls of at least this many frames run the packed 16-bit
+// kernel (two frames per lane).  It holds 128 frames per wave, so its drain
+// at the end of a call is the longest; measured faster than the 32-bit kernel
+// from 4,000,000 frames for N = 127 (1.10x) and at 11,000,000 frames for
+// N = 63 (1.09x), slower at 1,000,000 frames for N = 63 (0.73x)
+static int64_t packed_min_frames(int N) { return N > 64 ? 4000000 : 8000000; }
+
 // the kernel of a decode of F frames: the small-batch kernel (three waves per
 // 64 frames) when it is registered and F gives each CU at most 128 frames
 // (measured on the 127-bit codes: 2.7x faster up to 64 frames per CU, 1.2x at
@@ -109,6 +118,8 @@ static const bch::SpecKernel *spec_for(const bch_decoder_s *d, int64_t F)
 {
     if (d->spec_small && ((d->prm.flags & BCH_DEC_SMALL_ALWAYS) || F <= (int64_t)d->n_cu * 128))
         return d->spec_small;
+    if (d->spec_packed && F >= packed_min_frames(d->N))
+        return d->spec_packed;
     return d->spec;
 }
 
@@ -165,6 +176,65 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
     else
         e = k->launch(s, d->n_cu, waves, stream);
     return e == hipSuccess ? BCH_OK : hip_fail(e, "specialised kernel launch");
+}
+
+// the mixed-code kernel for decoders decs[0..n) in this order (nine-branch
+// restart-mode specialised decoders of one precision), or null
+static const bch::MixKernel *mixed_kernel_of(const bch_decoder *decs, int n)
+{
+    if (n < 2 || n > MIX_MAXC)
+        return nullptr;
+    uint64_t fps[MIX_MAXC];
+    for (int c = 0; c < n; c++) {
+        const bch_decoder_s *d = decs[c];
+        if (!d || !d->spec || d->prm.n_branches != 9 || d->prm.mode != BCH_MODE_RESTART ||
+            d->prm.precision != decs[0]->prm.precision || (d->prm.flags & BCH_DEC_NO_MIXED_KERNEL))
+            return nullptr;
+        fps[c] = d->fingerprint;
+    }
+    return find_mix_kernel(fps, n, decs[0]->prm.precision);
+}
+
+// one code-keyed prepass and one persistent kernel over every frame of the mix
+static int mixed_fused(const bch::MixKernel *k, const bch_decoder *decs, int n_codes, const uint8_t *code_idx,
+                       const void *llr, int64_t ld, int64_t F, const uint8_t *d_o, uint64_t *bits, int64_t bits_ld,
+                       uint8_t *iters, uint8_t *flags, void *workspace, hipStream_t stream)
+{
+    int dps[MIX_MAXC];
+    int nb = 0;
+    MixLaunch L{};
+    L.n_codes = n_codes;
+    L.bbase[0] = 0;
+    for (int c = 0; c < n_codes; c++) {
+        const bch_decoder_s *d = decs[c];
+        dps[c] = shift_period(d->N);
+        nb += dps[c];
+        L.bbase[c + 1] = nb;
+        L.alpha[c] = d->prm.alpha;
+        L.max_iter[c] = d->prm.max_iter;
+        L.weight[c] = (float)(9 * d->E);
+        L.two_slots[c] = d->N <= 64 ? 1 : 0;
+    }
+    BucketWs w = bucket_ws_carve(workspace, F, nb);
+    hipError_t e = launch_bucketing_mixed(d_o, code_idx, n_codes, dps, F, w, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "mixed bucketing prepass");
+    L.llr = llr;
+    L.ld = ld;
+    L.order = w.order;
+    L.bcur = w.cursor;
+    L.bend = w.end;
+    L.counts = w.counts;
+    L.n_buckets = nb;
+    L.bits = bits;
+    L.bits_ld = bits_ld;
+    L.iters = iters;
+    L.flags = flags;
+    // one wave per SIMD, no more waves than the frames can occupy
+    const int n_cu = decs[0]->n_cu;
+    const int64_t most = (F + 63) / 64 + nb;
+    e = most < (int64_t)n_cu * 4 ? k->launch(L, 1, (int)most, stream) : k->launch(L, n_cu, 4, stream);
+    return e == hipSuccess ? BCH_OK : hip_fail(e, "mixed-code kernel launch");
 }
 
 }  // namespace bch
@@ -423,7 +493,10 @@ int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params,
         return fail(BCH_EINVAL, "unknown precision");
     if ((q.flags & BCH_DEC_SMALL_ALWAYS) && (q.flags & BCH_DEC_SMALL_NEVER))
         return fail(BCH_EINVAL, "BCH_DEC_SMALL_ALWAYS and BCH_DEC_SMALL_NEVER exclude each other");
-    if (q.flags & ~(BCH_DEC_FORCE_GENERIC | BCH_DEC_PACKED16 | BCH_DEC_SMALL_ALWAYS | BCH_DEC_SMALL_NEVER))
+    if ((q.flags & BCH_DEC_PACKED16) && (q.flags & BCH_DEC_UNPACKED16))
+        return fail(BCH_EINVAL, "BCH_DEC_PACKED16 and BCH_DEC_UNPACKED16 exclude each other");
+    if (q.flags & ~(BCH_DEC_FORCE_GENERIC | BCH_DEC_PACKED16 | BCH_DEC_SMALL_ALWAYS | BCH_DEC_SMALL_NEVER |
+                    BCH_DEC_UNPACKED16 | BCH_DEC_NO_MIXED_KERNEL))
         return fail(BCH_EINVAL, "unknown decoder flags");
     if (p.E > 65535)
         return fail(BCH_EUNSUPPORTED, "too many edges");
@@ -486,7 +559,10 @@ int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params,
         d->spec = find_spec_kernel(p, q, packed ? 1 : 0);
         if (d->spec && !packed && !(q.flags & BCH_DEC_SMALL_NEVER))
             d->spec_small = find_spec_kernel(p, q, 2);
+        if (d->spec && !packed && q.precision == BCH_FIX8 && !(q.flags & BCH_DEC_UNPACKED16))
+            d->spec_packed = find_spec_kernel(p, q, 1);
     }
+    d->fingerprint = pcm_fingerprint(p);
     if (hipDeviceGetAttribute(&d->n_cu, hipDeviceAttributeMultiprocessorCount, d->dev) != hipSuccess ||
         d->n_cu <= 0)
         d->n_cu = 256;
@@ -667,6 +743,9 @@ int bch_mixed_decode_batch(const bch_decoder *decs, int n_codes, const uint8_t *
     const size_t need = bch_mixed_workspace_size(decs, n_codes, F);
     if (!workspace || ws_bytes < need)
         return fail(BCH_ENOMEM, "workspace too small");
+    if (const bch::MixKernel *k = mixed_kernel_of(decs, n_codes))
+        return mixed_fused(k, decs, n_codes, code_idx, llr, ld, F, d_o, bits, bits_ld, iters, flags, workspace,
+                           stream);
     char *ws = static_cast<char *>(workspace);
     for (int c = 0; c < n_codes; c++) {
         int rc = spec_decode(decs[c], llr, ld, F, d_o, code_idx, c, bits, bits_ld, iters, flags, nullptr, ws,
@@ -676,6 +755,14 @@ int bch_mixed_decode_batch(const bch_decoder *decs, int n_codes, const uint8_t *
         ws += spec_ws_bytes(decs[c], F);
     }
     return BCH_OK;
+}
+
+const char *bch_mixed_kernel_name(const bch_decoder *decs, int n_codes)
+{
+    if (!decs || n_codes < 1 || n_codes > BCH_MAX_MIX)
+        return "";
+    const bch::MixKernel *k = mixed_kernel_of(decs, n_codes);
+    return k ? k->name : "per-code";
 }
 
 int bch_osd_decode_device(bch_decoder dec, const float *llr, int64_t ld, int64_t F, int order,

@@ -8,28 +8,49 @@
 //      block (LDS counters).
 // Frames keep their input order inside a (block, bucket) up to the LDS-atomic
 // ranks; no result depends on that order (every frame is decoded on its own).
-// With a code index, only the frames of one code of a mixed batch are taken.
+// With a code index, either only the frames of one code of a mixed batch are
+// taken, or (mixed-code kernels) every frame of codes 0..n_codes-1 goes to
+// bucket base[code] + d_o mod d_p of its code.
 #include <hip/hip_runtime.h>
 
+#include "mix_launch.h"
 #include "spec_launch.h"
 
 namespace bch {
 
 namespace {
 
-constexpr int MAXB = 64;
+constexpr int MAXB = 128;
 constexpr int BLK = 2048;   // frames per counting block
 constexpr int TPB = 256;    // threads per counting block
 constexpr int SCAN = 1024;  // threads of the scan workgroup
 
-__device__ __forceinline__ int bucket_of(const uint8_t *d_o, int64_t f, int dp, int use)
+// which frames go to which bucket: one code (code_idx null, or the frames
+// with code_idx == code), buckets d_o mod dp (or all in bucket 0 when !use);
+// or, with n_codes > 0, every frame of code c < n_codes to bucket
+// base[c] + d_o mod dps[c]
+struct BucketMap {
+    const uint8_t *code_idx;
+    int code, dp, use;
+    int n_codes;
+    int base[MIX_MAXC + 1];
+    int dps[MIX_MAXC];
+};
+
+// bucket of frame f, or -1 if the map does not take it
+__device__ __forceinline__ int bucket_of(const uint8_t *d_o, int64_t f, const BucketMap &m)
 {
-    return use ? (int)d_o[f] % dp : 0;
+    if (m.n_codes > 0) {
+        const int c = m.code_idx[f];
+        return c < m.n_codes ? m.base[c] + (int)d_o[f] % m.dps[c] : -1;
+    }
+    if (m.code_idx && m.code_idx[f] != m.code)
+        return -1;
+    return m.use ? (int)d_o[f] % m.dp : 0;
 }
 
-__global__ void __launch_bounds__(TPB) bucket_count(const uint8_t *__restrict__ d_o,
-                                                    const uint8_t *__restrict__ code_idx, int code, int64_t F,
-                                                    int dp, int use, int *__restrict__ blk_hist)
+__global__ void __launch_bounds__(TPB) bucket_count(const uint8_t *__restrict__ d_o, BucketMap m, int64_t F,
+                                                    int nb, int *__restrict__ blk_hist)
 {
     __shared__ int h[MAXB];
     if (threadIdx.x < MAXB)
@@ -38,12 +59,15 @@ __global__ void __launch_bounds__(TPB) bucket_count(const uint8_t *__restrict__ 
     const int64_t base = (int64_t)blockIdx.x * BLK;
     for (int k = threadIdx.x; k < BLK; k += TPB) {
         const int64_t f = base + k;
-        if (f < F && (!code_idx || code_idx[f] == code))
-            atomicAdd(&h[bucket_of(d_o, f, dp, use)], 1);
+        if (f < F) {
+            const int b = bucket_of(d_o, f, m);
+            if (b >= 0)
+                atomicAdd(&h[b], 1);
+        }
     }
     __syncthreads();
-    if (threadIdx.x < dp)
-        blk_hist[(size_t)blockIdx.x * dp + threadIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < nb)
+        blk_hist[(size_t)blockIdx.x * nb + threadIdx.x] = h[threadIdx.x];
 }
 
 // one workgroup: per-block offsets in bucket-major order, bucket slices
@@ -90,20 +114,22 @@ __global__ void __launch_bounds__(SCAN) bucket_scan(int *__restrict__ blk_hist, 
     }
 }
 
-__global__ void __launch_bounds__(TPB) bucket_place(const uint8_t *__restrict__ d_o,
-                                                    const uint8_t *__restrict__ code_idx, int code, int64_t F,
-                                                    int dp, int use, const int *__restrict__ blk_off, BucketWs w)
+__global__ void __launch_bounds__(TPB) bucket_place(const uint8_t *__restrict__ d_o, BucketMap m, int64_t F,
+                                                    int nb, const int *__restrict__ blk_off, BucketWs w)
 {
     __shared__ int h[MAXB];
     if (threadIdx.x < MAXB)
-        h[threadIdx.x] = threadIdx.x < dp ? w.cursor[threadIdx.x] + blk_off[(size_t)blockIdx.x * dp + threadIdx.x] : 0;
+        h[threadIdx.x] = threadIdx.x < nb ? w.cursor[threadIdx.x] + blk_off[(size_t)blockIdx.x * nb + threadIdx.x] : 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * BLK;
     for (int k = threadIdx.x; k < BLK; k += TPB) {
         const int64_t f = base + k;
-        if (f < F && (!code_idx || code_idx[f] == code)) {
-            const int pos = atomicAdd(&h[bucket_of(d_o, f, dp, use)], 1);
-            w.order[pos] = (int)f;
+        if (f < F) {
+            const int b = bucket_of(d_o, f, m);
+            if (b >= 0) {
+                const int pos = atomicAdd(&h[b], 1);
+                w.order[pos] = (int)f;
+            }
         }
     }
 }
@@ -136,18 +162,44 @@ BucketWs bucket_ws_carve(void *ws, int64_t F, int dp)
     return w;
 }
 
+static hipError_t run_bucketing(const uint8_t *d_o, const BucketMap &m, int64_t F, int nb, const BucketWs &w,
+                                hipStream_t stream)
+{
+    if (nb < 1 || nb > MAXB || F <= 0)
+        return hipErrorInvalidValue;
+    const int nblk = (int)n_blocks(F);
+    hipLaunchKernelGGL(bucket_count, dim3(nblk), dim3(TPB), 0, stream, d_o, m, F, nb, w.blk_hist);
+    hipLaunchKernelGGL(bucket_scan, dim3(1), dim3(SCAN), 0, stream, w.blk_hist, nblk, nb, w);
+    hipLaunchKernelGGL(bucket_place, dim3(nblk), dim3(TPB), 0, stream, d_o, m, F, nb, w.blk_hist, w);
+    return hipGetLastError();
+}
+
 hipError_t launch_bucketing(const uint8_t *d_o, const uint8_t *code_idx, int code, int64_t F, int dp,
                             int use_offsets, const BucketWs &w, hipStream_t stream)
 {
-    if (dp > MAXB || F <= 0)
+    BucketMap m{};
+    m.code_idx = code_idx;
+    m.code = code;
+    m.dp = dp;
+    m.use = use_offsets;
+    m.n_codes = 0;
+    return run_bucketing(d_o, m, F, dp, w, stream);
+}
+
+hipError_t launch_bucketing_mixed(const uint8_t *d_o, const uint8_t *code_idx, int n_codes, const int *dps,
+                                  int64_t F, const BucketWs &w, hipStream_t stream)
+{
+    if (n_codes < 1 || n_codes > MIX_MAXC || code_idx == nullptr)
         return hipErrorInvalidValue;
-    const int nblk = (int)n_blocks(F);
-    hipLaunchKernelGGL(bucket_count, dim3(nblk), dim3(TPB), 0, stream, d_o, code_idx, code, F, dp, use_offsets,
-                       w.blk_hist);
-    hipLaunchKernelGGL(bucket_scan, dim3(1), dim3(SCAN), 0, stream, w.blk_hist, nblk, dp, w);
-    hipLaunchKernelGGL(bucket_place, dim3(nblk), dim3(TPB), 0, stream, d_o, code_idx, code, F, dp, use_offsets,
-                       w.blk_hist, w);
-    return hipGetLastError();
+    BucketMap m{};
+    m.code_idx = code_idx;
+    m.n_codes = n_codes;
+    m.base[0] = 0;
+    for (int c = 0; c < n_codes; c++) {
+        m.dps[c] = dps[c];
+        m.base[c + 1] = m.base[c] + dps[c];
+    }
+    return run_bucketing(d_o, m, F, m.base[n_codes], w, stream);
 }
 
 }  // namespace bch

@@ -41,5 +41,10 @@ BucketWs bucket_ws_carve(void *ws, int64_t F, int dp);
 // code_idx (may be null): only frames with code_idx[f] == code are taken.
 hipError_t launch_bucketing(const uint8_t *d_o, const uint8_t *code_idx, int code, int64_t F, int dp,
                             int use_offsets, const BucketWs &w, hipStream_t stream);
+// Mixed-code prepass: frame f of code c = code_idx[f] < n_codes goes to bucket
+// base[c] + d_o mod dps[c], base[0] = 0, base[c + 1] = base[c] + dps[c] (at
+// most 128 buckets); the workspace is carved for that many buckets.
+hipError_t launch_bucketing_mixed(const uint8_t *d_o, const uint8_t *code_idx, int n_codes, const int *dps,
+                                  int64_t F, const BucketWs &w, hipStream_t stream);
 
 }  // namespace bch

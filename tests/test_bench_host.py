@@ -69,3 +69,44 @@ def test_workload_table():
     assert frames == 4_000_000 and precisions == ["fp32", "fix8"]
     assert abs(sum(bench.WORKLOADS["mixed"][5]) - 1.0) < 1e-12
     assert bench.VALU_PEAK_OPS == 256 * 128 * 2.4e9 and bench.HBM_PEAK_BYTES == 8.0e12
+
+
+def test_wilson_interval():
+    lo, hi = bench.wilson(0, 100)
+    assert lo == 0.0 and 0.03 < hi < 0.04
+    lo, hi = bench.wilson(50, 100)
+    assert abs((lo + hi) / 2 - 0.5) < 1e-12 and 0.40 < lo < 0.41
+    assert bench.wilson(0, 0) == [0.0, 1.0]
+
+
+def test_cpu_leg_pairs_oracle_and_gpu_fer():
+    """The CPU leg on stub samples whose 'GPU' outcomes are the oracle's own:
+    every frame identical, oracle and GPU error rates equal per point."""
+    import oracle
+    import synth
+    from tests.helpers import oracle_code, oracle_hopt
+
+    class StubPcm:
+        M = 33
+
+        def dense(self):
+            return oracle_hopt("bch63_45", 33)
+
+    oc = oracle_code("bch63_45")
+    H = oracle_hopt("bch63_45", 33)
+    samples = []
+    for e in (2.0, 4.0):
+        fr = synth.frames("bch63_45", 600, e, seed=3)
+        for prec, kind in (("fp32", oracle.KIND_FAST), ("fix8", oracle.KIND_FIXED)):
+            x = fr.llr if prec == "fp32" else oracle.quantize(fr.llr, 4.0)
+            c, it, cv = oracle.decode_batch(H, oc.Hstd, x, fr.d_o, 9, 0.75, 8, oracle.R1, kind=kind, threads=4)
+            samples.append(bench.Sample("bch63_45", prec, e, x, fr.d_o, bench.pack(c), it.astype(np.uint8),
+                                        cv.astype(np.uint8), bench.pack(fr.codewords)))
+    out = bench.cpu_baseline(samples, {"bch63_45": StubPcm()}, 0.6, 1e8)
+    assert out["kind"] == "oracle" and out["value"] > 0 and out["cores"] >= 1
+    assert out["by_precision"]["fp32"]["identical_fraction"] == 1.0
+    assert out["by_precision"]["fix8"]["identical_fraction"] == 1.0
+    assert len(out["fer_paired"]) == 4
+    for p in out["fer_paired"]:
+        assert p["oracle_fer"] == p["gpu_fer"] and p["identical"] == p["frames"] >= 256
+        assert p["oracle_ci95"][0] <= p["oracle_fer"] <= p["oracle_ci95"][1]

@@ -49,3 +49,46 @@ def test_tune_layout_cache_and_results(B, tmp_path, monkeypatch, prec):
     torch.cuda.synchronize()
     for x, y in zip(a[:3], b[:3]):
         assert torch.equal(x, y)
+
+
+def test_alpha_search_argmin_and_bracket(B, tmp_path, monkeypatch):
+    """The alpha search returns the least frame error rate of its table, the
+    table brackets it (the grid widened until it does), and the result is
+    cached under the code, rows and I_m."""
+    from paper_2412_20828_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tuning.json"))
+    name, rows = "bch127_99", 33
+    d = B.CODE_DEFS[name]
+    code = B.Code(d.m, d.prim, d.t)
+    pcm = B.Pcm.build(code, target_rows=rows, seed=1)
+    e = autotune.search_alpha(code, pcm, name, rows, frames=60_000, grid=[0.9, 0.95, 1.0])
+    fer = {float(a): v for a, v in e["fer"].items()}
+    assert e["fer"]["%.2f" % e["alpha"]] == min(fer.values())
+    assert e["bracketed"] and min(fer) < e["alpha"] < max(fer)
+    assert e["ebn0"] == autotune.ALPHA_EBN0[127]
+    assert autotune.tuned_alpha(name, rows) == e["alpha"]
+    assert autotune.tuned_alpha(name, rows, max_iter=4) == 0.75  # nothing cached for I_m = 4
+
+
+@pytest.mark.parametrize("name,rows", [("bch63_45", 33), ("bch63_36", 122), ("bch127_64", 72), ("bch127_99", 33)])
+def test_parity_at_the_tuned_alpha(B, name, rows):
+    """Each code decoded with the alpha the search cached (as the workloads'
+    --alpha tuned does) against the oracle at that alpha."""
+    import oracle
+    from paper_2412_20828_amd import autotune
+    from tests.helpers import compare_with_oracle, oracle_code, oracle_hopt
+    alpha = autotune.tuned_alpha(name, rows)
+    assert autotune.alpha_key(name, rows, 8) in autotune.load(), "no cached alpha for %s" % name
+    d = B.CODE_DEFS[name]
+    code = B.Code(d.m, d.prim, d.t)
+    pcm = B.Pcm.build(code, target_rows=rows, seed=1)
+    dec = B.Decoder(code, pcm, n_branches=9, alpha=alpha, max_iter=8)
+    oc = oracle_code(name)
+    H = oracle_hopt(name, rows)
+    fr = synth.frames(name, 64 * 5 + 3, 3.0, seed=33)
+    bits, it, fl, tr = dec.decode(torch.from_numpy(fr.llr).cuda(), torch.from_numpy(fr.d_o).cuda(), trace=True)
+    torch.cuda.synchronize()
+    res = oracle.decode_batch(H, oc.Hstd, fr.llr, fr.d_o, 9, alpha, 8, oracle.R1, threads=8, trace=True)
+    words = B.unpack_bits(bits.cpu().numpy().view("uint64"), code.N)
+    compare_with_oracle(words, it.cpu().numpy(), fl.cpu().numpy(), tr.cpu().numpy(), *res,
+                        onestep=(H, oc.Hstd, fr.llr, fr.d_o, 9, alpha))

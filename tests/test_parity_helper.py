@@ -81,3 +81,27 @@ def test_near_zero_after_the_divergence_does_not_excuse():
     g[0, 0, 2] = 2.5
     g[0, 2, 2] = -1e-9
     assert compare_with_oracle(gw, orc_it, np.array([0]), g, orc_c, orc_it, orc_cv, tr) == (1, 1)
+
+
+def test_flip_inside_the_measured_drift_is_a_tie():
+    """With the GPU trace, a coordinate at 3e-5 of the frame's scale that
+    flips where the GPU trajectory deviates by 6e-5 is a tie under a 1e-3
+    trajectory bound, not under the edge-memory bound at iteration 2 (3e-5),
+    and not when the deviation elsewhere exceeds the bound."""
+    N, T = 7, 2
+    tr = np.array([[[4.0, -3.0, 2.5, 3.0, -2.0, 5.0, 2.0],
+                    [5.0, -4.0, 1.5e-4, 3.5, -2.5, 5.0, 2.5]]])
+    orc_c = (tr[:, -1] < 0).astype(np.uint8)
+    orc_it, orc_cv = np.array([T]), np.array([False])
+    g = np.zeros((1, T, 8), np.float32)
+    g[0, :, :N] = tr[0]
+    g[0, 1, 2] = -1.5e-4  # deviation 3e-4 / 5 = 6e-5 at iteration 2
+    gw = orc_c.copy()
+    gw[0, 2] ^= 1
+    assert compare_with_oracle(gw, orc_it, np.array([0]), g, orc_c, orc_it, orc_cv, tr, traj_tol=1e-3) == (1, 1)
+    # the edge-memory bound at iteration 2 is 3e-5: the same flip is beyond it
+    with pytest.raises(AssertionError, match="without a tie"):
+        compare_with_oracle(gw, orc_it, np.array([0]), g, orc_c, orc_it, orc_cv, tr)
+    g[0, 1, 0] = 5.1  # plus a deviation of 0.1 / 5.1 = 2e-2 elsewhere: beyond the flat bound too
+    with pytest.raises(AssertionError, match="without a tie"):
+        compare_with_oracle(gw, orc_it, np.array([0]), g, orc_c, orc_it, orc_cv, tr, traj_tol=1e-3)
