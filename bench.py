@@ -386,6 +386,8 @@ def build_mixed(args, B, torch, dev, stream, codes, probs, lohi, precisions, see
             pts, ops, info = [], 0.0, 0
             for k, ((name, _), (code, pcm)) in enumerate(zip(codes, objs)):
                 sel = ci == k
+                if not sel.any():
+                    continue
                 pts.append({"code": name, "precision": prec, "ebn0": "U[%g,%g]" % tuple(lohi),
                             "frames": int(sel.sum()), "fer": float(err[sel].mean()),
                             "avg_iters": float(iters[sel].mean()), "undetected": float((err & conv)[sel].mean())})
@@ -398,6 +400,8 @@ def build_mixed(args, B, torch, dev, stream, codes, probs, lohi, precisions, see
             W, I, C = bits.cpu().numpy().view(np.uint64), it.cpu().numpy(), fl.cpu().numpy()
             for k, (name, _) in enumerate(codes):
                 sel = np.nonzero(ci == k)[0][:KEEP]
+                if sel.size == 0:
+                    continue
                 x = llr[sel].copy() if prec == "fp32" else inp[torch.from_numpy(sel).to(dev)].cpu().numpy()
                 out.append(Sample(name, prec, "U[%g,%g]" % tuple(lohi), x, d_o[sel].copy(), W[sel], I[sel], C[sel],
                                   cwp[sel]))
@@ -755,6 +759,7 @@ def main():
     ap.add_argument("--write-alpha", action="store_true", help="alpha workload: cache the results in tuning.json")
     ap.add_argument("--mixed-path", default="fused", choices=["fused", "per-code"],
                     help="mixed workload: the mixed-code kernel (one launch) or one launch per code")
+    ap.add_argument("--mix-probs", default="", help="mixed workload: per-code frame probabilities, comma-separated")
     ap.add_argument("--requests", type=int, default=3000, help="requests of the serving workload")
     ap.add_argument("--osd", default="device", choices=["device", "host"], help="serving: where OSD-2 runs")
     ap.add_argument("--slots", type=int, default=3, help="serving: batches in flight (slots)")
@@ -808,7 +813,13 @@ def main():
     t0 = time.time()
     if args.workload == "mixed":
         lohi = [float(x) for x in args.ebn0.split(":")]
-        items, mats = build_mixed(args, B, torch, dev, stream, codes, wl[5], lohi, precisions, 4000)
+        probs = [float(p) for p in args.mix_probs.split(",")] if args.mix_probs else wl[5]
+        if len(probs) != len(codes) or min(probs) < 0 or abs(sum(probs) - 1.0) > 1e-9:
+            raise SystemExit("--mix-probs: %d probabilities >= 0 that sum to 1" % len(codes))
+        if args.mix_probs:
+            wdesc = wdesc.split(" in one call")[0].split(", per frame")[0] + ", per frame " + ", ".join(
+                "%g%% %s" % (100 * p, n) for p, (n, _) in zip(probs, codes)) + " in one call"
+        items, mats = build_mixed(args, B, torch, dev, stream, codes, probs, lohi, precisions, 4000)
         ebn0_desc = "U[%g, %g] per frame" % tuple(lohi)
     else:
         lo, hi, st = (float(x) for x in args.ebn0.split(":"))

@@ -127,12 +127,30 @@ _pmats = {}
 
 def encode(spec: CodeSpec, msg: np.ndarray) -> np.ndarray:
     """Systematic codewords [F][N] (uint8): parity in columns 0..N-K-1, message
-    bits in columns N-K..N-1 (coefficient of x^j in column j)."""
+    bits in columns N-K..N-1 (coefficient of x^j in column j).
+
+    The parity is the XOR of the parity rows of the set message bits, taken a
+    message byte at a time from a 256-entry table per byte: exact integer work
+    with no BLAS call, so that generator threads running side by side (several
+    blocks of a workload at once) stay deterministic."""
     if spec.name not in _pmats:
-        _pmats[spec.name] = _parity_matrix(spec).astype(np.float32)
-    P = _pmats[spec.name]
-    par = (msg.astype(np.float32) @ P).astype(np.int64) & 1
-    return np.concatenate([par.astype(np.uint8), msg.astype(np.uint8)], axis=1)
+        Pb = np.packbits(_parity_matrix(spec), axis=1, bitorder="little")  # [K][ceil(r/8)]
+        nbytes = (spec.K + 7) // 8
+        T = np.zeros((nbytes, 256, Pb.shape[1]), dtype=np.uint8)
+        for j in range(nbytes):
+            for b in range(8):
+                k = 8 * j + b
+                if k < spec.K:
+                    sel = (np.arange(256) >> b) & 1 == 1
+                    T[j, sel] ^= Pb[k]
+        _pmats[spec.name] = T
+    T = _pmats[spec.name]
+    mp = np.packbits(msg.astype(np.uint8), axis=1, bitorder="little")  # [F][ceil(K/8)]
+    par = np.zeros((msg.shape[0], T.shape[2]), dtype=np.uint8)
+    for j in range(T.shape[0]):
+        par ^= T[j][mp[:, j]]
+    bits = np.unpackbits(par, axis=1, count=spec.N - spec.K, bitorder="little")
+    return np.concatenate([bits, msg.astype(np.uint8)], axis=1)
 
 
 @dataclass

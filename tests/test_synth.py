@@ -76,3 +76,23 @@ def test_request_trace_distribution():
     assert e.min() >= 2.0 and e.max() <= 5.0
     fr = synth.request_frames(["bch63_36", "bch63_45", "bch127_64", "bch127_99"], tr[5], 1, 5)
     assert fr.llr.shape[0] == tr[5].frames
+
+
+def test_threaded_encoding_is_deterministic_with_torch_loaded():
+    """Messages encoded side by side in threads (as the benchmark's generator
+    threads do) give the codewords of a one-at-a-time encoding, and every one
+    is valid.  With torch loaded, concurrent float BLAS calls from numpy
+    threads have returned corrupted rows; the encoder is integer-only for that
+    reason."""
+    import torch  # noqa: F401  (loaded for its effect on the BLAS/OpenMP runtime)
+    from concurrent.futures import ThreadPoolExecutor
+    m, p, t = synth.CODES["bch127_99"]
+    c = oracle.Code(m, p, t)
+    spec = synth.code("bch127_99")
+    msgs = [np.random.default_rng(k).integers(0, 2, (300000, spec.K), dtype=np.uint8) for k in range(8)]
+    with ThreadPoolExecutor(8) as ex:
+        par = list(ex.map(lambda x: synth.encode(spec, x), msgs))
+    for x, cw in zip(msgs, par):
+        assert np.array_equal(cw, synth.encode(spec, x))
+        assert np.array_equal(cw[:, c.N - c.K:], x)
+        assert not ((cw[:4096].astype(int) @ c.Hstd.T.astype(int)) % 2).any()
