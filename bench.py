@@ -88,7 +88,8 @@ TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written, family, source hash)
 }
 KERNEL_FAMILIES = {
     "one_wave": (["csrc/nms_spec_fp32.inc", "csrc/nms_spec_rot.inc", "csrc/nms_spec_cursor.inc"],
-                 ["body_source_ilp", "syndrome_source", "_sign_masks", "_parity", "_MED3U"]),
+                 ["body_source_ilp", "_min_steps", "syndrome_source", "_sign_masks", "_parity", "_MED3U",
+                  "ILP_ROWS"]),
     "pk16": (["csrc/nms_spec_pk16.inc", "csrc/nms_spec_rot.inc", "csrc/nms_spec_cursor.inc"],
              ["body_source_pk16", "syndrome_source", "_parity"]),
 }
@@ -107,7 +108,7 @@ def kernel_src_hash(family):
             outer.update(hashlib.sha256(fh.read()).digest())
     for name in funcs:
         obj = getattr(gen_spec, name)
-        text = obj if isinstance(obj, str) else inspect.getsource(obj)
+        text = obj if isinstance(obj, str) else (inspect.getsource(obj) if callable(obj) else repr(obj))
         outer.update(hashlib.sha256(text.encode()).digest())
     return outer.hexdigest()[:16]
 
@@ -245,8 +246,8 @@ def make_decoder(args, B, code, pcm, name, rows, prec):
     autotuner's cached layout and grid (--tuned)."""
     precision = B.FIX8 if prec == "fix8" else B.FP32
     flags = (B.FORCE_GENERIC if args.generic else 0) | (B.PACKED16 if args.packed16 and prec == "fix8" else 0)
-    if getattr(args, "mixed_path", "fused") == "per-code":
-        flags |= B.NO_MIXED_KERNEL
+    path = getattr(args, "mixed_path", "auto")
+    flags |= {"per-code": B.NO_MIXED_KERNEL, "fused": B.MIXED_KERNEL}.get(path, 0)
     alpha = workload_alpha(args, name, rows)
     if args.tuned and not args.generic:
         from paper_2412_20828_amd import autotune
@@ -376,7 +377,8 @@ def build_mixed(args, B, torch, dev, stream, codes, probs, lohi, precisions, see
         item = Item("mixed", prec, F, lambda st=stream, mix=mix, inp=inp, bits=bits, it=it, fl=fl, ws=ws:
                     mix.decode_into(ci_d, inp, d_o_d, bits, it, fl, ws, stream=st))
         # the mixed-code kernel's name, or per-code launches of this precision
-        item.kernel = mix.kernel_name if mix.kernel_name != "per-code" else "per-code_%s" % prec
+        kname = mix.kernel_name(F)
+        item.kernel = kname if kname != "per-code" else "per-code_%s" % prec
 
         def stats(prec=prec, bits=bits, it=it, fl=fl):
             w = bits.cpu().numpy().view(np.uint64)
@@ -757,8 +759,9 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="capture each launch of the step in a HIP graph once and replay it in the timed loop")
     ap.add_argument("--write-alpha", action="store_true", help="alpha workload: cache the results in tuning.json")
-    ap.add_argument("--mixed-path", default="fused", choices=["fused", "per-code"],
-                    help="mixed workload: the mixed-code kernel (one launch) or one launch per code")
+    ap.add_argument("--mixed-path", default="auto", choices=["auto", "fused", "per-code"],
+                    help="mixed workload: the library's choice by batch size, the mixed-code kernel (one "
+                         "launch) or one launch per code")
     ap.add_argument("--mix-probs", default="", help="mixed workload: per-code frame probabilities, comma-separated")
     ap.add_argument("--requests", type=int, default=3000, help="requests of the serving workload")
     ap.add_argument("--osd", default="device", choices=["device", "host"], help="serving: where OSD-2 runs")

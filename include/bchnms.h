@@ -159,8 +159,12 @@ enum {
                                   Both flags together, or any other bit, give BCH_EINVAL */
     BCH_DEC_UNPACKED16 = 16,   /* BCH_FIX8: never the packed 16-bit kernel (with
                                   BCH_DEC_PACKED16: BCH_EINVAL) */
-    BCH_DEC_NO_MIXED_KERNEL = 32 /* a mixed-code call that includes this decoder runs one
-                                  prepass and kernel per code (bch_mixed_decode_batch) */
+    BCH_DEC_NO_MIXED_KERNEL = 32, /* a mixed-code call that includes this decoder runs one
+                                   prepass and kernel per code (bch_mixed_decode_batch) */
+    BCH_DEC_MIXED_KERNEL = 64    /* a mixed-code call that includes this decoder runs the
+                                   mixed-code kernel at any batch size (where registered and
+                                   no decoder of the call has BCH_DEC_NO_MIXED_KERNEL; with
+                                   BCH_DEC_NO_MIXED_KERNEL on the same decoder: BCH_EINVAL) */
 };
 typedef struct {
     int n_branches; /* 1, 3 or 9 */
@@ -236,25 +240,30 @@ int bch_decoder_set_tuning(bch_decoder dec, int waves_per_cu);
  * device [F][bits_ld] uint64, bits_ld >= every ceil(N/64); iters, flags: as
  * bch_nms_decode_batch; F <= BCH_MAX_FRAMES.  When the library carries a
  * mixed-code kernel for these decoders' matrices in this order (nine-branch,
- * restart-mode decoders of one precision, none with BCH_DEC_NO_MIXED_KERNEL),
+ * restart-mode decoders of one precision, none with BCH_DEC_NO_MIXED_KERNEL)
+ * and F < BCH_MIXED_KERNEL_MAX_FRAMES (or a decoder has BCH_DEC_MIXED_KERNEL),
  * the call enqueues one prepass that buckets every frame by (code, d_o) and
  * one persistent kernel whose waves take frames of any code (the batching
  * pattern of one launch for a mixed batch); otherwise one prepass and one
- * persistent kernel per code.  No host synchronisation, no memset: the call
+ * persistent kernel per code.  The size limit is where the two paths cross
+ * over: one launch saves the per-code launch tails, which dominate small
+ * batches, while each code's own kernel holds fewer registers (the 63-bit
+ * codes' kernels run three waves per SIMD, the mixed kernel one).  No host synchronisation, no memset: the call
  * can be captured in a HIP graph and replayed.  Per-frame results do not
  * depend on the mix or the path: each frame decodes exactly as alone.
  */
 #define BCH_MAX_MIX 8
+#define BCH_MIXED_KERNEL_MAX_FRAMES 3000000
 size_t bch_mixed_workspace_size(const bch_decoder *decs, int n_codes, int64_t F);
 int bch_mixed_decode_batch(const bch_decoder *decs, int n_codes, const uint8_t *code_idx, const void *llr,
                            int64_t ld, int64_t F, const uint8_t *d_o, uint64_t *bits, int64_t bits_ld,
                            uint8_t *iters, uint8_t *flags, void *workspace, size_t ws_bytes,
                            hipStream_t stream);
 
-/* Name of the kernel a mixed call over decs[0..n_codes) runs: the mixed-code
- * kernel's, or "per-code" ("" for bad arguments); static, owned by the
- * library. */
-const char *bch_mixed_kernel_name(const bch_decoder *decs, int n_codes);
+/* Name of the kernel a mixed call of F frames over decs[0..n_codes) runs:
+ * the mixed-code kernel's, or "per-code" ("" for bad arguments); static,
+ * owned by the library. */
+const char *bch_mixed_kernel_name(const bch_decoder *decs, int n_codes, int64_t F);
 
 /* Syndrome test of eq. 5 with the code's standard PCM: ok[f] = 1 iff
  * H c_f^T = 0.  bits: device [F][ceil(N/64)] uint64; ok: device [F] uint8. */

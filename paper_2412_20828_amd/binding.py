@@ -26,6 +26,8 @@ SMALL_ALWAYS = 4
 SMALL_NEVER = 8
 UNPACKED16 = 16
 NO_MIXED_KERNEL = 32
+MIXED_KERNEL = 64
+MIXED_KERNEL_MAX_FRAMES = 3_000_000
 
 SYMBOLS = [
     "bch_last_error", "bch_load_code", "bch_code_info", "bch_code_export", "bch_code_destroy",
@@ -103,7 +105,7 @@ def lib():
     L.bch_mixed_workspace_size.argtypes = [P, i32, i64]
     L.bch_mixed_workspace_size.restype = ctypes.c_size_t
     L.bch_mixed_decode_batch.argtypes = [P, i32, P, P, i64, i64, P, P, i64, P, P, P, ctypes.c_size_t, P]
-    L.bch_mixed_kernel_name.argtypes = [P, i32]
+    L.bch_mixed_kernel_name.argtypes = [P, i32, ctypes.c_int64]
     L.bch_mixed_kernel_name.restype = ctypes.c_char_p
     L.bch_osd_decode_device.argtypes = [P, P, i64, i64, i32, P, P, i64, P]
     L.bch_mixed_osd_decode.argtypes = [P, i32, P, P, i64, i64, i32, P, P, i64, P]
@@ -330,10 +332,9 @@ class MixedDecoder:
     def workspace_size(self, F: int) -> int:
         return int(lib().bch_mixed_workspace_size(self._arr, len(self.decoders), F))
 
-    @property
-    def kernel_name(self) -> str:
-        """The mixed-code kernel the call runs, or "per-code"."""
-        return lib().bch_mixed_kernel_name(self._arr, len(self.decoders)).decode()
+    def kernel_name(self, F: int) -> str:
+        """The mixed-code kernel a call of F frames runs, or "per-code"."""
+        return lib().bch_mixed_kernel_name(self._arr, len(self.decoders), F).decode()
 
     def decode_into(self, code_idx, llr, d_o, bits, iters, flags, workspace, stream=None):
         F, ld = llr.shape

@@ -180,18 +180,22 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
 
 // the mixed-code kernel for decoders decs[0..n) in this order (nine-branch
 // restart-mode specialised decoders of one precision), or null
-static const bch::MixKernel *mixed_kernel_of(const bch_decoder *decs, int n)
+static const bch::MixKernel *mixed_kernel_of(const bch_decoder *decs, int n, int64_t F)
 {
     if (n < 2 || n > MIX_MAXC)
         return nullptr;
     uint64_t fps[MIX_MAXC];
+    bool forced = false;
     for (int c = 0; c < n; c++) {
         const bch_decoder_s *d = decs[c];
         if (!d || !d->spec || d->prm.n_branches != 9 || d->prm.mode != BCH_MODE_RESTART ||
             d->prm.precision != decs[0]->prm.precision || (d->prm.flags & BCH_DEC_NO_MIXED_KERNEL))
             return nullptr;
+        forced = forced || (d->prm.flags & BCH_DEC_MIXED_KERNEL);
         fps[c] = d->fingerprint;
     }
+    if (!forced && F >= BCH_MIXED_KERNEL_MAX_FRAMES)
+        return nullptr;
     return find_mix_kernel(fps, n, decs[0]->prm.precision);
 }
 
@@ -495,8 +499,10 @@ int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params,
         return fail(BCH_EINVAL, "BCH_DEC_SMALL_ALWAYS and BCH_DEC_SMALL_NEVER exclude each other");
     if ((q.flags & BCH_DEC_PACKED16) && (q.flags & BCH_DEC_UNPACKED16))
         return fail(BCH_EINVAL, "BCH_DEC_PACKED16 and BCH_DEC_UNPACKED16 exclude each other");
+    if ((q.flags & BCH_DEC_NO_MIXED_KERNEL) && (q.flags & BCH_DEC_MIXED_KERNEL))
+        return fail(BCH_EINVAL, "BCH_DEC_NO_MIXED_KERNEL and BCH_DEC_MIXED_KERNEL exclude each other");
     if (q.flags & ~(BCH_DEC_FORCE_GENERIC | BCH_DEC_PACKED16 | BCH_DEC_SMALL_ALWAYS | BCH_DEC_SMALL_NEVER |
-                    BCH_DEC_UNPACKED16 | BCH_DEC_NO_MIXED_KERNEL))
+                    BCH_DEC_UNPACKED16 | BCH_DEC_NO_MIXED_KERNEL | BCH_DEC_MIXED_KERNEL))
         return fail(BCH_EINVAL, "unknown decoder flags");
     if (p.E > 65535)
         return fail(BCH_EUNSUPPORTED, "too many edges");
@@ -743,7 +749,7 @@ int bch_mixed_decode_batch(const bch_decoder *decs, int n_codes, const uint8_t *
     const size_t need = bch_mixed_workspace_size(decs, n_codes, F);
     if (!workspace || ws_bytes < need)
         return fail(BCH_ENOMEM, "workspace too small");
-    if (const bch::MixKernel *k = mixed_kernel_of(decs, n_codes))
+    if (const bch::MixKernel *k = mixed_kernel_of(decs, n_codes, F))
         return mixed_fused(k, decs, n_codes, code_idx, llr, ld, F, d_o, bits, bits_ld, iters, flags, workspace,
                            stream);
     char *ws = static_cast<char *>(workspace);
@@ -757,11 +763,11 @@ int bch_mixed_decode_batch(const bch_decoder *decs, int n_codes, const uint8_t *
     return BCH_OK;
 }
 
-const char *bch_mixed_kernel_name(const bch_decoder *decs, int n_codes)
+const char *bch_mixed_kernel_name(const bch_decoder *decs, int n_codes, int64_t F)
 {
-    if (!decs || n_codes < 1 || n_codes > BCH_MAX_MIX)
+    if (!decs || n_codes < 1 || n_codes > BCH_MAX_MIX || F < 0)
         return "";
-    const bch::MixKernel *k = mixed_kernel_of(decs, n_codes);
+    const bch::MixKernel *k = mixed_kernel_of(decs, n_codes, F);
     return k ? k->name : "per-code";
 }
 

@@ -65,7 +65,13 @@ MIXES = [
 ]
 # rows whose min1/min2 chains the one-wave-per-SIMD (N = 127) row functions
 # interleave (2 measured best: 4 gave 2% less)
-ILP_ROWS = 2
+# rows whose min searches interleave in the one-wave kernels: one with the
+# triple search (its steps hold two independent triples); two with the
+# entry-by-entry chain of the mixed-code kernel, whose dual-frame length-63
+# path keeps that kernel at the register limit (the triple search's extra live
+# values spill there and measured slower)
+ILP_ROWS = 1
+MIX_ILP_ROWS = 2
 
 CODE_DEFS = {
     "bch63_36": (6, 0b1000011, 5),
@@ -126,14 +132,23 @@ def fingerprint(H: np.ndarray) -> int:
     return h
 
 
-# The min1/min2 chain runs on the bit patterns of the magnitudes: non-negative
-# floats order as their bit patterns, so integer min and med3 give the same
-# values as the float ones, and on gfx950 they issue beside the float med3 of
-# the c2v selection instead of competing with it.  The min/max tree below is
-# matched to a single v_med3_u32.
+# The min1/min2 search runs on the bit patterns of the magnitudes: non-negative
+# floats order as their bit patterns, so integer min, min3 and med3 give the
+# same values as the float ones, with none of the input canonicalisation the
+# compiler adds around a float min.  med3u is a min/max tree that the compiler
+# matches to one v_med3_u32 in the entry-by-entry chain; med3i is the
+# instruction itself, for the triple search, where the compiler would share a
+# min of the same operands between a triple's least value and its median and
+# split the median into four instructions.
 _MED3U = """__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c)
 {
     return min(max(a, b), max(min(a, b), c));
+}
+__device__ __forceinline__ uint32_t med3i(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    __asm__("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
 }
 """
 
@@ -158,26 +173,93 @@ def _parity(S, masks):
     return "__builtin_popcount(%s)" % " ^ ".join(terms)
 
 
+def _min_steps(cols, sfx, val, tree=True, pair_merge=True):
+    """Steps (lists of statements) that leave u1<sfx> <= u2<sfx>, the two
+    least of the row's values val(c), c in cols (integer form of non-negative
+    floats).
+
+    tree=False: one entry per step (u2 = med3(u1, u2, x), u1 = min(u1, x)),
+    two instructions per entry and two live values.  tree=True: entries go in
+    threes: min3 and med3 of a triple give its least two in two instructions;
+    two triples merge into the running pair with u1 = min3(u1, m_a, m_b) and
+    u2 = min(med3(u1, m_a, m_b), min3(u2, s_a, s_b)) (the second least of
+    three sorted pairs is the middle of their leasts unless the pair holding
+    the least has a smaller second): eight instructions per six entries where
+    the chain takes twelve, for four more live values (pair_merge=False: one
+    triple at a time, five per three).  The two least values of a set do not
+    depend on the order they are found in, so every form gives the same
+    u1, u2."""
+    w = len(cols)
+    if w < 2:
+        raise ValueError("a check row needs at least two entries")
+    v = [val(c) for c in cols]
+    u1, u2 = "u1" + sfx, "u2" + sfx
+    if not tree:
+        steps = [["uint32_t %s = min(%s, %s), %s = max(%s, %s);" % (u1, v[0], v[1], u2, v[0], v[1])]]
+        for x in v[2:]:
+            steps.append(["%s = med3u(%s, %s, %s); %s = min(%s, %s);" % (u2, u1, u2, x, u1, u1, x)])
+        return steps
+    n3 = w // 3
+    tri = [v[3 * k:3 * k + 3] for k in range(n3)]
+    rest = v[3 * n3:]
+    steps = []
+
+    def triple(k, x):
+        return ["const uint32_t m%s_%d = min(min(%s, %s), %s), s%s_%d = med3i(%s, %s, %s);"
+                % (sfx, k, x[0], x[1], x[2], sfx, k, x[0], x[1], x[2])]
+
+    if n3 == 0:
+        steps.append(["uint32_t %s = min(%s, %s), %s = max(%s, %s);" % (u1, v[0], v[1], u2, v[0], v[1])])
+        rest = v[2:]
+    elif n3 == 1 or not pair_merge:
+        steps.append(triple(0, tri[0]))
+        steps.append(["uint32_t %s = m%s_0, %s = s%s_0;" % (u1, sfx, u2, sfx)])
+        for k in range(1, n3):
+            steps.append(triple(k, tri[k]))
+            steps.append(["%s = med3i(%s, m%s_%d, min(%s, s%s_%d)); %s = min(%s, m%s_%d);"
+                          % (u2, u1, sfx, k, u2, sfx, k, u1, u1, sfx, k)])
+    else:
+        steps.append(triple(0, tri[0]) + triple(1, tri[1]))
+        steps.append(["uint32_t %s = min(m%s_0, m%s_1), %s = med3i(m%s_0, m%s_1, min(s%s_0, s%s_1));"
+                      % (u1, sfx, sfx, u2, sfx, sfx, sfx, sfx)])
+        k = 2
+        while k + 1 < n3:
+            steps.append(triple(k, tri[k]) + triple(k + 1, tri[k + 1]))
+            a, b = k, k + 1
+            steps.append(["%s = min(med3i(%s, m%s_%d, m%s_%d), min(min(%s, s%s_%d), s%s_%d)); "
+                          "%s = min(min(%s, m%s_%d), m%s_%d);"
+                          % (u2, u1, sfx, a, sfx, b, u2, sfx, a, sfx, b, u1, u1, sfx, a, sfx, b)])
+            k += 2
+        if k < n3:
+            steps.append(triple(k, tri[k]))
+            steps.append(["%s = med3i(%s, m%s_%d, min(%s, s%s_%d)); %s = min(%s, m%s_%d);"
+                          % (u2, u1, sfx, k, u2, sfx, k, u1, u1, sfx, k)])
+    for x in rest:
+        steps.append(["%s = med3i(%s, %s, %s); %s = min(%s, %s);" % (u2, u1, u2, x, u1, u1, x)])
+    return steps
+
+
 def _forward(cols):
-    """Lines of a row's min1 <= min2 chain over A[cols] in integer form,
-    ending with float m1, m2."""
-    c0, c1 = cols[0], cols[1]
-    out = ["        uint32_t u1 = min(__float_as_uint(A[%d]), __float_as_uint(A[%d])), "
-           "u2 = max(__float_as_uint(A[%d]), __float_as_uint(A[%d]));" % (c0, c1, c0, c1)]
-    for c in cols[2:]:
-        out.append("        u2 = med3u(u1, u2, __float_as_uint(A[%d])); u1 = min(u1, __float_as_uint(A[%d]));" % (c, c))
+    """Lines of a row's min1 <= min2 search over A[cols] in integer form,
+    ending with float m1, m2: the entry-by-entry chain, whose two live values
+    suit the kernels that run several waves per SIMD within 168 registers."""
+    out = []
+    for st in _min_steps(cols, "", lambda c: "__float_as_uint(A[%d])" % c, tree=False):
+        out += ["        " + x for x in st]
     out.append("        const float m1 = __uint_as_float(u1), m2 = __uint_as_float(u2);")
     return out
 
 
-def body_source_ilp(H: np.ndarray, fix8: bool = False, group: int = 2) -> str:
+def body_source_ilp(H: np.ndarray, fix8: bool = False, group: int = 1, tree: bool = True) -> str:
     """The row function (accumulating form, FP32 or fixed point) with
     independent work side by side, for kernels that run one wave per SIMD and
     so have no other wave to issue while an instruction waits for its
-    predecessor: the min1/min2 chains of `group` consecutive rows interleaved
-    step by step, and the c2v selections of each row two edges at a time,
-    pinned by scheduling barriers.  Every column is still updated by its rows
-    in ascending order."""
+    predecessor: the min1/min2 searches of `group` consecutive rows
+    interleaved step by step (tree: by triples, see _min_steps, whose two
+    independent triples per step already give the search its parallel work;
+    else entry by entry), and the c2v selections of each row two edges at a
+    time, pinned by scheduling barriers.  Every column is still updated by its
+    rows in ascending order."""
     M, N = H.shape
     out = [_MED3U, "__device__ __forceinline__ void body(const float *__restrict__ A, "
            "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
@@ -190,15 +272,11 @@ def body_source_ilp(H: np.ndarray, fix8: bool = False, group: int = 2) -> str:
             cols[r] = cs
             cnt = _parity("S", _sign_masks(cs, N))
             out.append("        const float sg%d = __uint_as_float(0x3f800000u | ((%s) << 31));" % (r, cnt))
-            c0, c1 = cs[0], cs[1]
-            out.append("        uint32_t u1_%d = min(__float_as_uint(A[%d]), __float_as_uint(A[%d])), "
-                       "u2_%d = max(__float_as_uint(A[%d]), __float_as_uint(A[%d]));" % (r, c0, c1, r, c0, c1))
-        for k in range(2, max(len(c) for c in cols.values())):
+        steps = {r: _min_steps(cols[r], "_%d" % r, lambda c: "__float_as_uint(A[%d])" % c, tree=tree) for r in cols}
+        for k in range(max(len(st) for st in steps.values())):
             for r in cols:
-                if k < len(cols[r]):
-                    c = cols[r][k]
-                    out.append("        u2_%d = med3u(u1_%d, u2_%d, __float_as_uint(A[%d])); "
-                               "u1_%d = min(u1_%d, __float_as_uint(A[%d]));" % (r, r, r, c, r, r, c))
+                if k < len(steps[r]):
+                    out += ["        " + x for x in steps[r][k]]
             out.append("        __builtin_amdgcn_sched_barrier(0);")
         for r in cols:
             out.append("        const float m1_%d = __uint_as_float(u1_%d), m2_%d = __uint_as_float(u2_%d);"
@@ -312,15 +390,11 @@ def body_source_dual(H: np.ndarray, fix8: bool = False) -> str:
         for f in (0, 1):
             out.append("        const float sg%d = __uint_as_float(0x3f800000u | ((%s) << 31));"
                        % (f, _parity("S%d" % f, masks)))
-        c0, c1 = cols[0], cols[1]
-        for f in (0, 1):
-            out.append("        uint32_t u1_%d = min(__float_as_uint(A%d[%d]), __float_as_uint(A%d[%d])), "
-                       "u2_%d = max(__float_as_uint(A%d[%d]), __float_as_uint(A%d[%d]));"
-                       % (f, f, c0, f, c1, f, f, c0, f, c1))
-        for c in cols[2:]:
+        steps = [_min_steps(cols, "_%d" % f, lambda c, f=f: "__float_as_uint(A%d[%d])" % (f, c), tree=False)
+                 for f in (0, 1)]
+        for k in range(len(steps[0])):
             for f in (0, 1):
-                out.append("        u2_%d = med3u(u1_%d, u2_%d, __float_as_uint(A%d[%d])); "
-                           "u1_%d = min(u1_%d, __float_as_uint(A%d[%d]));" % (f, f, f, f, c, f, f, f, c))
+                out += ["        " + x for x in steps[f][k]]
         for f in (0, 1):
             out.append("        const float m1_%d = __uint_as_float(u1_%d), m2_%d = __uint_as_float(u2_%d);"
                        % (f, f, f, f))
@@ -359,7 +433,7 @@ def mixed_source(ns, parts, prec, out_dir):
         with open(body_path, "w") as fh:
             fh.write("// generated: %s, H_o %d x %d, %d edges (code %d of %s)\n" % (name, M, N, int(H.sum()), k, ns))
             if N > 64:
-                fh.write(body_source_ilp(H, fix8=bool(prec), group=ILP_ROWS))
+                fh.write(body_source_ilp(H, fix8=bool(prec), group=MIX_ILP_ROWS, tree=False))
             else:
                 fh.write(body_source_dual(H, fix8=bool(prec)))
             fh.write("\n\n" + syndrome_source(Hs) + "\n")
@@ -491,7 +565,7 @@ def generate(stage1_lib: str, out_dir: str):
                 fh.write(body_source_pk16(H, B))
             else:
                 if regacc and N > 64:
-                    fh.write(body_source_ilp(H, fix8=bool(prec), group=ILP_ROWS))
+                    fh.write(body_source_ilp(H, fix8=bool(prec), group=ILP_ROWS, tree=True))
                 else:
                     fh.write(body_source_fix8(H, regacc) if prec else body_source(H, regacc))
             fh.write("\n\n" + syndrome_source(Hs) + "\n")

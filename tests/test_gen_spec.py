@@ -48,3 +48,57 @@ def test_sign_masks_one_bit_per_coordinate(N):
 def test_parity_expression_shape():
     e = gen_spec._parity("S", [0x5, 0, 0x80000000])
     assert e == "__builtin_popcount((S[0] & 0x00000005u) ^ (S[2] & 0x80000000u))"
+
+
+def _run_min_steps(cols, vals, **kw):
+    """Evaluate the generated statements of a min1/min2 search in Python:
+    min, max and med3 (median of three) on the given integers."""
+    env = {}
+    med3 = lambda a, b, c: sorted([a, b, c])[1]  # noqa: E731
+    glb = {"min": min, "max": max, "med3u": med3, "med3i": med3, "V": vals}
+    for step in gen_spec._min_steps(cols, "_x", lambda c: "V[%d]" % c, **kw):
+        for line in step:
+            line = line.replace("const uint32_t ", "").replace("uint32_t ", "")
+            for stmt in filter(None, (x.strip() for x in line.split(";"))):
+                parts, depth, cur = [], 0, ""
+                for ch in stmt:  # split "a = x, b = y" at top-level commas
+                    depth += (ch == "(") - (ch == ")")
+                    if ch == "," and depth == 0:
+                        parts.append(cur)
+                        cur = ""
+                    else:
+                        cur += ch
+                parts.append(cur)
+                for p in parts:
+                    lhs, rhs = p.split("=", 1)
+                    env[lhs.strip()] = eval(rhs, glb, env)
+    return env["u1_x"], env["u2_x"]
+
+
+@pytest.mark.parametrize("kw", [{}, {"tree": False}, {"pair_merge": False}])
+def test_min_search_forms_give_the_two_least(kw):
+    """Every form of the generated min1/min2 search (triples merged in pairs,
+    one at a time, or the entry-by-entry chain) leaves the least and second
+    least value of the row, for row weights 2..60, with many ties (values
+    drawn from a handful) and without."""
+    rng = np.random.default_rng(9)
+    for w in range(2, 61):
+        for _ in range(60):
+            small = rng.random() < 0.5
+            vals = [int(x) for x in (rng.integers(0, 4, w) if small else rng.integers(0, 1 << 31, w))]
+            cols = rng.permutation(w).tolist()
+            assert _run_min_steps(cols, vals, **kw) == tuple(sorted(vals)[:2]), (w, vals)
+
+
+def test_min_search_instruction_counts():
+    """The triple search spends 8 instructions per 6 entries where the chain
+    spends 12: min/max/med3 calls in the generated statements, a min of a min
+    counted once (the compiler's min3)."""
+    import re
+    cols = list(range(24))
+
+    def count(kw):
+        lines = [x for st in gen_spec._min_steps(cols, "", lambda c: "V[%d]" % c, **kw) for x in st]
+        return sum(len(re.findall(r"\b(min|max|med3[ui])\(", x)) - x.count("min(min(") for x in lines)
+    assert count({"tree": False}) == 2 * 24 - 2
+    assert count({}) == 8 * 24 // 6 - 1  # the first two triples merge with three, not four

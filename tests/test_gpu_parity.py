@@ -98,7 +98,7 @@ def test_small_batch_kernel_selection(B):
     assert f63.kernel_name(8_000_000) == "spec_bch63_36_m122_b9_fix8_pk16"
     gen = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8, flags=B.FORCE_GENERIC)
     assert gen.kernel_name(100) == "generic"
-    for bad in (B.SMALL_ALWAYS | B.SMALL_NEVER, 64):
+    for bad in (B.SMALL_ALWAYS | B.SMALL_NEVER, 128):
         with pytest.raises(B.BchError):
             B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8, flags=bad)
 
@@ -787,8 +787,9 @@ def test_device_osd_skip_and_hybrid(B):
 
 def test_mixed_full_size_sampled(B):
     """The mixed workload at its full size: 16,000,000 interleaved frames in one
-    call per precision; 200 sampled frames per code against the oracle (FP64
-    with the tie rule for FP32, bit-exact for int8)."""
+    call per precision, on per-code launches (the default at this size) and on
+    the mixed-code kernel; 200 sampled frames per code against the oracle
+    (FP64 with the tie rule for FP32, bit-exact for int8)."""
     names = [n for n, _ in MIX]
     F = 16_000_000
     blocks = 32
@@ -802,9 +803,10 @@ def test_mixed_full_size_sampled(B):
     ci = torch.from_numpy(code_idx).cuda()
     d_o = torch.from_numpy(d_o_h).cuda()
     rng = np.random.default_rng(5)
-    for precision in (0, 1):
+    for precision, flags in ((0, 0), (1, 0), (0, B.MIXED_KERNEL), (1, B.MIXED_KERNEL)):
         objs = [lib_objects(B, n, r) for n, r in MIX]
-        decs = [B.Decoder(c, p, n_branches=9, max_iter=8, precision=precision) for c, p in objs]
+        decs = [B.Decoder(c, p, n_branches=9, max_iter=8, precision=precision, flags=flags) for c, p in objs]
+        assert B.MixedDecoder(decs).kernel_name(F).startswith("mix_") == bool(flags)
         inp = llr
         if precision == B.FIX8:
             inp = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
@@ -838,16 +840,26 @@ def test_mixed_full_size_sampled(B):
 # ------------------------------------------------------------ the mixed-code kernel
 def test_mixed_kernel_selection(B):
     """The three codes of the mixed workload in this order have a mixed-code
-    kernel per precision; a decoder flagged NO_MIXED_KERNEL, another order or
-    a single code runs per-code launches."""
+    kernel per precision, run below the size limit (at any size with
+    MIXED_KERNEL); a decoder flagged NO_MIXED_KERNEL, another order or a
+    single code runs per-code launches."""
     objs = [lib_objects(B, n, r) for n, r in MIX]
+    lim = B.MIXED_KERNEL_MAX_FRAMES
     for precision, suffix in ((0, ""), (1, "_fix8")):
+        name = "mix_127_64_m72_127_99_m33_63_36_m122" + suffix
         decs = [B.Decoder(c, p, n_branches=9, max_iter=8, precision=precision) for c, p in objs]
-        assert B.MixedDecoder(decs).kernel_name == "mix_127_64_m72_127_99_m33_63_36_m122" + suffix
-        assert B.MixedDecoder(decs[::-1]).kernel_name == "per-code"
-        assert B.MixedDecoder(decs[:1]).kernel_name == "per-code"
+        assert B.MixedDecoder(decs).kernel_name(100) == B.MixedDecoder(decs).kernel_name(lim - 1) == name
+        assert B.MixedDecoder(decs).kernel_name(lim) == "per-code"
+        assert B.MixedDecoder(decs[::-1]).kernel_name(100) == "per-code"
+        assert B.MixedDecoder(decs[:1]).kernel_name(100) == "per-code"
         off = B.Decoder(*objs[0], n_branches=9, max_iter=8, precision=precision, flags=B.NO_MIXED_KERNEL)
-        assert B.MixedDecoder([off] + decs[1:]).kernel_name == "per-code"
+        assert B.MixedDecoder([off] + decs[1:]).kernel_name(100) == "per-code"
+        on = B.Decoder(*objs[1], n_branches=9, max_iter=8, precision=precision, flags=B.MIXED_KERNEL)
+        assert B.MixedDecoder([decs[0], on, decs[2]]).kernel_name(10 ** 8) == name
+        assert B.MixedDecoder([off, on, decs[2]]).kernel_name(100) == "per-code"
+        with pytest.raises(B.BchError):
+            B.Decoder(*objs[0], n_branches=9, max_iter=8, precision=precision,
+                      flags=B.MIXED_KERNEL | B.NO_MIXED_KERNEL)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -864,7 +876,7 @@ def test_mixed_kernel_equals_per_code_launches(B, precision, mix_p):
     mk = lambda fl: [B.Decoder(c, p, n_branches=9, alpha=a, max_iter=m, precision=precision, flags=fl)
                      for (c, p), a, m in zip(objs, alphas, its)]
     fused, per = B.MixedDecoder(mk(0)), B.MixedDecoder(mk(B.NO_MIXED_KERNEL))
-    assert fused.kernel_name.startswith("mix_") and per.kernel_name == "per-code"
+    assert fused.kernel_name(F).startswith("mix_") and per.kernel_name(F) == "per-code"
     probs = [p for p in mix_p]
     mf = synth.mixed_frames([n for n, _ in MIX], F, 71, probs, 1.5, 5.0)
     ci = mf.code_idx.copy()
