@@ -430,7 +430,8 @@ def run_serve(args):
     names = [n for n, _ in SERVE_CODES]
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     eng = serving.Engine(SERVE_CODES, slot_frames=args.slot_frames, n_slots=args.slots, osd_order=2, osd_on=args.osd,
-                         osd_threads=max(1, min(16, threads) - 2), tuned=not args.generic)
+                         osd_threads=max(1, min(16, threads) - 2), tuned=not args.generic,
+                         graph=not args.serve_eager)
     t0 = time.time()
     tr = synth.request_trace(args.requests, 5000, len(names), 2.0, 5.0)
     with ThreadPoolExecutor(min(16, os.cpu_count() or 4)) as ex:
@@ -473,8 +474,12 @@ def run_serve(args):
         "config": {"workload": "serving: %d requests, Poisson arrivals, round(2^(12U)) frames each, code uniform "
                                "over BCH(63,36) H_o 122x63, (63,45) 33x63, (127,64) 72x127, (127,99) 33x127, "
                                "Eb/N0 U[2, 5] dB per request; enhanced NMS 9 branches, max 8 iterations on the "
-                               "GPU (%d slots of %d frames), OSD-2 for NMS failures %s"
-                               % (len(tr), args.slots, args.slot_frames, "on the GPU" if args.osd == "device" else
+                               "GPU (%d slots of %d frames, %s), OSD-2 for NMS failures %s"
+                               % (len(tr), args.slots, args.slot_frames,
+                                  "each step launched code by code" if args.serve_eager else
+                                  "each step one captured graph: one mixed-code kernel, then device OSD"
+                                  if args.osd == "device" else "each step one captured graph of the mixed-code "
+                                  "kernel", "on the GPU" if args.osd == "device" else
                                   "on %d host threads" % max(1, min(16, threads) - 2)),
                    "mean_request_frames": mean_frames},
         "saturation": sat,
@@ -767,6 +772,8 @@ def main():
     ap.add_argument("--osd", default="device", choices=["device", "host"], help="serving: where OSD-2 runs")
     ap.add_argument("--slots", type=int, default=3, help="serving: batches in flight (slots)")
     ap.add_argument("--slot-frames", type=int, default=1 << 16, help="serving: frame capacity of a slot")
+    ap.add_argument("--serve-eager", action="store_true",
+                    help="serving: launch each slot step code by code instead of replaying its captured graph")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()

@@ -56,15 +56,14 @@ SPECS = [
     ("bch63_45", 33, 1, 1, 0, 5),
     ("bch63_36", 122, 1, 1, 0, 4),
 ]
-# mixed-code kernels: one persistent launch over frames of these codes (the
-# mixed workload's codes), FP32 and fixed point; code k of a mixed call is the
-# k-th matrix here
+# mixed-code kernels: one persistent launch over frames of these codes, code k
+# of a mixed call being the k-th matrix here: the mixed workload's codes (FP32
+# and fixed point) and the serving engine's four codes (FP32)
 MIXES = [
     ([("bch127_64", 72), ("bch127_99", 33), ("bch63_36", 122)], 0),
     ([("bch127_64", 72), ("bch127_99", 33), ("bch63_36", 122)], 1),
+    ([("bch63_36", 122), ("bch63_45", 33), ("bch127_64", 72), ("bch127_99", 33)], 0),
 ]
-# rows whose min1/min2 chains the one-wave-per-SIMD (N = 127) row functions
-# interleave (2 measured best: 4 gave 2% less)
 # rows whose min searches interleave in the one-wave kernels: one with the
 # triple search (its steps hold two independent triples); two with the
 # entry-by-entry chain of the mixed-code kernel, whose dual-frame length-63

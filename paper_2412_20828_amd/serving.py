@@ -24,11 +24,27 @@ of its frames have a decision.
 Every frame decodes exactly as it would alone: the kernel's arithmetic for a
 frame depends only on that frame's LLRs and offset, and OSD is deterministic.
 
-A slot uses 1 + (number of codes) streams.  HIP maps a process's streams onto
-GPU_MAX_HW_QUEUES hardware queues (4 by default), and streams that share a
-queue run in submission order, so with too few queues one slot's copies wait
-behind another slot's kernels.  A serving process should set the variable to
-at least hw_queues(n_slots, n_codes) before HIP initialises.
+With graph=True (the default) a slot's device work is also held as one HIP
+graph, captured once per slot when the engine starts: a mixed-code decode over
+the slot's whole capacity (frames past the batch carry a code index that names
+no decoder, so the prepass skips them; the engine's code set has a mixed-code
+kernel, so that is one prepass and one persistent kernel for every code of the
+batch) followed by the device OSD of the frames that did not converge.  A step
+of at least graph_min_frames frames replays it, with only the copies in and
+out, sized by the batch, enqueued beside the replay: one graph launch and
+three copies whatever the number of codes in the batch.  A smaller step (and
+every step with graph=False) decodes each code present by its own call on a
+stream of the slot's own: those calls pick the small-batch kernels, which
+spread a frame's nine branches over three waves and so finish a small batch
+about three times sooner than the one-wave mixed-code kernel.  The default
+limit, 128 frames per CU, is where the per-code calls leave those kernels.
+
+A slot uses 1 + (number of codes) streams (one with graph=True).  HIP maps a
+process's streams onto GPU_MAX_HW_QUEUES hardware queues (4 by default), and
+streams that share a queue run in submission order, so with too few queues
+one slot's copies wait behind another slot's kernels.  A serving process
+should set the variable to at least hw_queues(n_slots, n_codes) before HIP
+initialises.
 """
 from __future__ import annotations
 
@@ -89,6 +105,11 @@ class _Slot:
     h_iters: object
     h_flags: object
     wss: list               # per code workspace
+    h_ci: object = None     # graph mode: code index per frame (pinned), 255 past the batch
+    d_ci: object = None
+    ws_mix: object = None   # graph mode: workspace of the mixed call
+    graph: object = None    # graph mode: the slot's captured decode + OSD
+    prev_n: int = 0         # frames of the slot's previous batch (their code bytes are reset)
     members: list = field(default_factory=list)   # (request, offset)
     busy: bool = False
 
@@ -100,10 +121,13 @@ class Engine:
     (osd_on="host": each finished slot's failed frames go to one OSD call per
     code, spread over osd_threads native threads; calls run one at a time on
     a helper thread, so the scheduler never waits for them).  tuned: apply the
-    autotuner's cached launch shapes."""
+    autotuner's cached launch shapes.  graph: replay one captured HIP graph
+    per slot step of at least graph_min_frames frames (default 128 per CU;
+    see the module notes)."""
 
     def __init__(self, codes, slot_frames=1 << 16, n_slots=3, osd_order=2, osd_on="device", osd_threads=8,
-                 precision=B.FP32, max_iter=8, tuned=True, device="cuda", seed=0):
+                 precision=B.FP32, max_iter=8, tuned=True, device="cuda", seed=0, graph=True,
+                 graph_min_frames=None):
         import torch
         self.seed = seed  # key of the offsets the engine draws (bch_draw_offsets)
         self.torch = torch
@@ -158,8 +182,44 @@ class Engine:
                 h_bits=torch.empty((cap, 2), dtype=torch.int64, **pin),
                 h_iters=torch.empty(cap, dtype=torch.uint8, **pin), h_flags=torch.empty(cap, dtype=torch.uint8, **pin),
                 wss=[torch.empty(b, dtype=torch.uint8, device=self.dev) for b in ws_bytes]))
+        self.mix = B.MixedDecoder(self.decs)
+        self.graph = graph
+        if graph_min_frames is None:
+            graph_min_frames = 128 * torch.cuda.get_device_properties(self.dev).multi_processor_count
+        self.graph_min_frames = graph_min_frames
+        self.graph_steps = 0
+        if graph:
+            self._capture_graphs()
         self.launches = 0
         self.frames_launched = 0
+
+    def _slot_device_work(self, s: _Slot, stream):
+        """The device work of one slot step over its whole capacity: the
+        mixed-code decode, then device OSD of the frames left unconverged."""
+        self.mix.decode_into(s.d_ci, s.d_llr, s.d_do, s.d_bits, s.d_iters, s.d_flags, s.ws_mix, stream=stream)
+        if self.osd_order is not None and self.osd_on == "device":
+            self.mix.osd_into(s.d_ci, s.d_llr, self.osd_order, s.d_bits, skip=s.d_flags, stream=stream)
+
+    def _capture_graphs(self):
+        torch = self.torch
+        cap = self.cap
+        for s in self.slots:
+            s.h_ci = torch.full((cap,), 255, dtype=torch.uint8, pin_memory=True)
+            s.d_ci = torch.full((cap,), 255, dtype=torch.uint8, device=self.dev)
+            s.ws_mix = torch.empty(max(1, self.mix.workspace_size(cap)), dtype=torch.uint8, device=self.dev)
+            s.d_llr.zero_()
+            s.d_do.zero_()
+            # one eager pass outside the capture (first-use set-up of the
+            # library), then the capture on the slot's stream
+            s.stream.wait_stream(torch.cuda.current_stream(self.dev))
+            with torch.cuda.stream(s.stream):
+                self._slot_device_work(s, s.stream)
+            s.stream.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s.stream):
+                self._slot_device_work(s, torch.cuda.current_stream(self.dev))
+            s.graph = g
+        torch.cuda.synchronize(self.dev)
 
     # ------------------------------------------------------------ client side
     def submit(self, req: Request):
@@ -256,6 +316,30 @@ class Engine:
             r.t_admit = now
             s.members.append((r, off))
             pos[r.code] += F
+        if self.graph and n >= self.graph_min_frames:
+            # code bytes of this batch, and 255 over what the slot's previous
+            # replay used beyond it, so that the replay decodes exactly these
+            # frames
+            hc = s.h_ci.numpy()
+            for c in range(len(self.decs)):
+                hc[start[c]:start[c] + counts[c]] = c
+            top = max(n, s.prev_n)
+            hc[n:top] = 255
+            with torch.cuda.stream(s.stream):
+                s.d_llr[:n].copy_(s.h_llr[:n], non_blocking=True)
+                s.d_do[:n].copy_(s.h_do[:n], non_blocking=True)
+                s.d_ci[:top].copy_(s.h_ci[:top], non_blocking=True)
+                s.graph.replay()
+                s.h_bits[:n].copy_(s.d_bits[:n], non_blocking=True)
+                s.h_iters[:n].copy_(s.d_iters[:n], non_blocking=True)
+                s.h_flags[:n].copy_(s.d_flags[:n], non_blocking=True)
+            s.prev_n = n
+            self.graph_steps += 1
+            s.event.record(s.stream)
+            s.busy = True
+            self.launches += 1
+            self.frames_launched += n
+            return
         with torch.cuda.stream(s.stream):
             s.d_llr[:n].copy_(s.h_llr[:n], non_blocking=True)
             s.d_do[:n].copy_(s.h_do[:n], non_blocking=True)
