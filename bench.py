@@ -246,6 +246,7 @@ def make_decoder(args, B, code, pcm, name, rows, prec):
     autotuner's cached layout and grid (--tuned)."""
     precision = B.FIX8 if prec == "fix8" else B.FP32
     flags = (B.FORCE_GENERIC if args.generic else 0) | (B.PACKED16 if args.packed16 and prec == "fix8" else 0)
+    flags |= B.CHUNK_BUCKETS if getattr(args, "chunk_buckets", False) else 0
     path = getattr(args, "mixed_path", "auto")
     flags |= {"per-code": B.NO_MIXED_KERNEL, "fused": B.MIXED_KERNEL}.get(path, 0)
     alpha = workload_alpha(args, name, rows)
@@ -759,6 +760,8 @@ def main():
     ap.add_argument("--precision", default="", choices=["", "fp32", "fix8", "both"],
                     help="override the workload's precisions")
     ap.add_argument("--packed16", action="store_true", help="fixed point: the packed 16-bit kernels (two frames per lane)")
+    ap.add_argument("--chunk-buckets", action="store_true",
+                    help="decoders with CHUNK_BUCKETS: each XCD decodes its own chunks of the batch first")
     ap.add_argument("--alpha", default="0.75",
                     help='alpha of the FP32 decoders: a number, or "tuned" (the autotuner\'s cached search result)')
     ap.add_argument("--graph", action="store_true",

@@ -161,10 +161,17 @@ enum {
                                   BCH_DEC_PACKED16: BCH_EINVAL) */
     BCH_DEC_NO_MIXED_KERNEL = 32, /* a mixed-code call that includes this decoder runs one
                                    prepass and kernel per code (bch_mixed_decode_batch) */
-    BCH_DEC_MIXED_KERNEL = 64    /* a mixed-code call that includes this decoder runs the
+    BCH_DEC_MIXED_KERNEL = 64,   /* a mixed-code call that includes this decoder runs the
                                    mixed-code kernel at any batch size (where registered and
                                    no decoder of the call has BCH_DEC_NO_MIXED_KERNEL; with
                                    BCH_DEC_NO_MIXED_KERNEL on the same decoder: BCH_EINVAL) */
+    BCH_DEC_CHUNK_BUCKETS = 128  /* specialised decodes of at least 1,048,576 frames: the
+                                   prepass deals chunks of 65,536 frames round robin to eight
+                                   ranges, one per XCD, whose waves decode their own chunks
+                                   first, so each output cache line is filled by one XCD and
+                                   leaves its L2 whole (HBM writes of the packed 16-bit kernel
+                                   on the 127-bit sweep: 83 -> 48 bytes per frame, for about
+                                   2% more kernel time).  Same results */
 };
 typedef struct {
     int n_branches; /* 1, 3 or 9 */

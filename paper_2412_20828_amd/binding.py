@@ -27,6 +27,7 @@ SMALL_NEVER = 8
 UNPACKED16 = 16
 NO_MIXED_KERNEL = 32
 MIXED_KERNEL = 64
+CHUNK_BUCKETS = 128
 MIXED_KERNEL_MAX_FRAMES = 3_000_000
 
 SYMBOLS = [

@@ -124,9 +124,16 @@ static const bch::SpecKernel *spec_for(const bch_decoder_s *d, int64_t F)
 }
 
 // device workspace of one specialised decode of up to F frames
+static int spec_offsets(const bch_decoder_s *d) { return d->prm.n_branches > 1 ? shift_period(d->N) : 1; }
+
+static int spec_ranges(const bch_decoder_s *d, int64_t F)
+{
+    return bucket_ranges(F, (d->prm.flags & BCH_DEC_CHUNK_BUCKETS) != 0);
+}
+
 static size_t spec_ws_bytes(const bch_decoder_s *d, int64_t F)
 {
-    size_t n = align256(bucket_ws_bytes(F, shift_period(d->N)));
+    size_t n = align256(bucket_ws_bytes(F, spec_ranges(d, F) * spec_offsets(d)));
     if (d->spec->y_global)
         n += align256((size_t)d->n_cu * waves_of(d) * d->N * 64 * sizeof(float));
     return n;
@@ -139,9 +146,11 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
                        uint8_t *flags, void *trace, void *workspace, hipStream_t stream)
 {
     const int dp = shift_period(d->N);
+    const int ranges = spec_ranges(d, F);
+    const int nb = ranges * spec_offsets(d);
     char *ws = static_cast<char *>(workspace);
-    BucketWs w = bucket_ws_carve(ws, F, dp);
-    hipError_t e = launch_bucketing(d_o, code_idx, code, F, dp, d->prm.n_branches > 1, w, stream);
+    BucketWs w = bucket_ws_carve(ws, F, nb);
+    hipError_t e = launch_bucketing(d_o, code_idx, code, F, dp, d->prm.n_branches > 1, ranges, w, stream);
     if (e != hipSuccess)
         return hip_fail(e, "bucketing prepass");
     SpecLaunch s{};
@@ -150,14 +159,16 @@ static int spec_decode(const bch_decoder_s *d, const void *llr, int64_t ld, int6
     s.order = w.order;
     s.bcur = w.cursor;
     s.bend = w.end;
-    s.n_buckets = d->prm.n_branches > 1 ? dp : 1;
+    s.n_offsets = spec_offsets(d);
+    s.n_ranges = ranges;
+    s.n_buckets = nb;
     s.bits = bits;
     s.bits_ld = bits_ld;
     s.iters = iters;
     s.flags = flags;
     s.trace = trace;
     s.yscratch = d->spec->y_global
-                     ? reinterpret_cast<float *>(ws + align256(bucket_ws_bytes(F, dp)))
+                     ? reinterpret_cast<float *>(ws + align256(bucket_ws_bytes(F, nb)))
                      : nullptr;
     s.max_iter = d->prm.max_iter;
     s.alpha = d->prm.alpha;
@@ -502,7 +513,7 @@ int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params,
     if ((q.flags & BCH_DEC_NO_MIXED_KERNEL) && (q.flags & BCH_DEC_MIXED_KERNEL))
         return fail(BCH_EINVAL, "BCH_DEC_NO_MIXED_KERNEL and BCH_DEC_MIXED_KERNEL exclude each other");
     if (q.flags & ~(BCH_DEC_FORCE_GENERIC | BCH_DEC_PACKED16 | BCH_DEC_SMALL_ALWAYS | BCH_DEC_SMALL_NEVER |
-                    BCH_DEC_UNPACKED16 | BCH_DEC_NO_MIXED_KERNEL | BCH_DEC_MIXED_KERNEL))
+                    BCH_DEC_UNPACKED16 | BCH_DEC_NO_MIXED_KERNEL | BCH_DEC_MIXED_KERNEL | BCH_DEC_CHUNK_BUCKETS))
         return fail(BCH_EINVAL, "unknown decoder flags");
     if (p.E > 65535)
         return fail(BCH_EUNSUPPORTED, "too many edges");

@@ -20,18 +20,19 @@ namespace bch {
 
 namespace {
 
-constexpr int MAXB = 128;
+constexpr int MAXB = 512;
 constexpr int BLK = 2048;   // frames per counting block
 constexpr int TPB = 256;    // threads per counting block
 constexpr int SCAN = 1024;  // threads of the scan workgroup
 
 // which frames go to which bucket: one code (code_idx null, or the frames
-// with code_idx == code), buckets d_o mod dp (or all in bucket 0 when !use);
-// or, with n_codes > 0, every frame of code c < n_codes to bucket
-// base[c] + d_o mod dps[c]
+// with code_idx == code), bucket (f ranges / F) nofs + d_o mod dp (offset 0
+// when !use; nofs = dp, or 1 when !use); or, with n_codes > 0, every frame of
+// code c < n_codes to bucket base[c] + d_o mod dps[c]
 struct BucketMap {
     const uint8_t *code_idx;
-    int code, dp, use;
+    int code, dp, use, nofs, ranges;
+    int64_t F;
     int n_codes;
     int base[MIX_MAXC + 1];
     int dps[MIX_MAXC];
@@ -46,15 +47,16 @@ __device__ __forceinline__ int bucket_of(const uint8_t *d_o, int64_t f, const Bu
     }
     if (m.code_idx && m.code_idx[f] != m.code)
         return -1;
-    return m.use ? (int)d_o[f] % m.dp : 0;
+    const int r = m.ranges > 1 ? (int)((f >> kRangeChunkLog2) % m.ranges) : 0;
+    return r * m.nofs + (m.use ? (int)d_o[f] % m.dp : 0);
 }
 
 __global__ void __launch_bounds__(TPB) bucket_count(const uint8_t *__restrict__ d_o, BucketMap m, int64_t F,
                                                     int nb, int *__restrict__ blk_hist)
 {
     __shared__ int h[MAXB];
-    if (threadIdx.x < MAXB)
-        h[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < nb; i += TPB)
+        h[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * BLK;
     for (int k = threadIdx.x; k < BLK; k += TPB) {
@@ -66,8 +68,8 @@ __global__ void __launch_bounds__(TPB) bucket_count(const uint8_t *__restrict__ 
         }
     }
     __syncthreads();
-    if (threadIdx.x < nb)
-        blk_hist[(size_t)blockIdx.x * nb + threadIdx.x] = h[threadIdx.x];
+    for (int i = threadIdx.x; i < nb; i += TPB)
+        blk_hist[(size_t)blockIdx.x * nb + i] = h[i];
 }
 
 // one workgroup: per-block offsets in bucket-major order, bucket slices
@@ -118,8 +120,8 @@ __global__ void __launch_bounds__(TPB) bucket_place(const uint8_t *__restrict__ 
                                                     int nb, const int *__restrict__ blk_off, BucketWs w)
 {
     __shared__ int h[MAXB];
-    if (threadIdx.x < MAXB)
-        h[threadIdx.x] = threadIdx.x < nb ? w.cursor[threadIdx.x] + blk_off[(size_t)blockIdx.x * nb + threadIdx.x] : 0;
+    for (int i = threadIdx.x; i < nb; i += TPB)
+        h[i] = w.cursor[i] + blk_off[(size_t)blockIdx.x * nb + i];
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * BLK;
     for (int k = threadIdx.x; k < BLK; k += TPB) {
@@ -140,24 +142,24 @@ int64_t n_blocks(int64_t F) { return (F + BLK - 1) / BLK; }
 
 }  // namespace
 
-size_t bucket_ws_bytes(int64_t F, int dp)
+size_t bucket_ws_bytes(int64_t F, int nb)
 {
-    const size_t head = align16(sizeof(int) * 3 * (size_t)dp);
-    const size_t hist = align16(sizeof(int) * (size_t)n_blocks(F) * dp);
+    const size_t head = align16(sizeof(int) * 3 * (size_t)nb);
+    const size_t hist = align16(sizeof(int) * (size_t)n_blocks(F) * nb);
     return head + hist + align16((size_t)F * sizeof(int));
 }
 
-BucketWs bucket_ws_carve(void *ws, int64_t F, int dp)
+BucketWs bucket_ws_carve(void *ws, int64_t F, int nb)
 {
     BucketWs w;
     char *p = static_cast<char *>(ws);
     int *h = reinterpret_cast<int *>(p);
     w.counts = h;
-    w.cursor = h + dp;
-    w.end = h + 2 * dp;
-    p += align16(sizeof(int) * 3 * (size_t)dp);
+    w.cursor = h + nb;
+    w.end = h + 2 * nb;
+    p += align16(sizeof(int) * 3 * (size_t)nb);
     w.blk_hist = reinterpret_cast<int *>(p);
-    p += align16(sizeof(int) * (size_t)n_blocks(F) * dp);
+    p += align16(sizeof(int) * (size_t)n_blocks(F) * nb);
     w.order = reinterpret_cast<int *>(p);
     return w;
 }
@@ -175,15 +177,20 @@ static hipError_t run_bucketing(const uint8_t *d_o, const BucketMap &m, int64_t 
 }
 
 hipError_t launch_bucketing(const uint8_t *d_o, const uint8_t *code_idx, int code, int64_t F, int dp,
-                            int use_offsets, const BucketWs &w, hipStream_t stream)
+                            int use_offsets, int ranges, const BucketWs &w, hipStream_t stream)
 {
     BucketMap m{};
     m.code_idx = code_idx;
     m.code = code;
     m.dp = dp;
     m.use = use_offsets;
+    m.nofs = use_offsets ? dp : 1;
+    if (ranges < 1 || ranges > kRangeXcds)
+        return hipErrorInvalidValue;
+    m.ranges = ranges;
+    m.F = F;
     m.n_codes = 0;
-    return run_bucketing(d_o, m, F, dp, w, stream);
+    return run_bucketing(d_o, m, F, m.ranges * m.nofs, w, stream);
 }
 
 hipError_t launch_bucketing_mixed(const uint8_t *d_o, const uint8_t *code_idx, int n_codes, const int *dps,

@@ -98,7 +98,7 @@ def test_small_batch_kernel_selection(B):
     assert f63.kernel_name(8_000_000) == "spec_bch63_36_m122_b9_fix8_pk16"
     gen = B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8, flags=B.FORCE_GENERIC)
     assert gen.kernel_name(100) == "generic"
-    for bad in (B.SMALL_ALWAYS | B.SMALL_NEVER, 128):
+    for bad in (B.SMALL_ALWAYS | B.SMALL_NEVER, 256):
         with pytest.raises(B.BchError):
             B.Decoder(c, p, n_branches=9, mode=B.MODE_RESTART, alpha=0.75, max_iter=8, flags=bad)
 
@@ -197,6 +197,42 @@ def test_full_size_batches_sampled(B, name, rows, F, ebn0):
     res = oracle.decode_batch(H, oc.Hstd, llr_h, d_h, 9, 0.75, 8, oracle.R1, threads=8, trace=True)
     words = B.unpack_bits(bits.cpu().numpy().view(np.uint64)[idx], c.N)
     compare_with_oracle(words, it_h[idx], flg_h[idx], None, *res)
+
+
+@pytest.mark.parametrize("name,rows,nb,precision,flags", [("bch127_64", 72, 9, "fp32", 0),
+                                                         ("bch127_99", 33, 9, "fix8", "PACKED16"),
+                                                         ("bch127_99", 33, 9, "fix8", "UNPACKED16"),
+                                                         ("bch63_36", 122, 9, "fp32", 0),
+                                                         ("bch63_45", 33, 1, "fp32", 0)])
+def test_range_buckets_equal_chunked_calls(B, name, rows, nb, precision, flags):
+    """With CHUNK_BUCKETS, from 1,048,576 frames the prepass also deals
+    chunks of 65,536 frames to eight ranges, one per XCD.  Every frame of a
+    1,300,000-frame call (ranges of two or three chunks, the last one ragged)
+    must equal, in word, iteration count and flag, the same frame decoded in
+    calls of at most 500,000 frames (no ranges): nothing is lost, repeated or
+    decoded with another frame's offset (one branch: a single offset bucket
+    per range)."""
+    F, chunk = 1_300_000, 500_000
+    c, p = lib_objects(B, name, rows)
+    dec = B.Decoder(c, p, n_branches=nb, mode=B.MODE_RESTART, alpha=0.75, max_iter=8,
+                    precision=B.FIX8 if precision == "fix8" else B.FP32,
+                    flags=(getattr(B, flags) if flags else 0) | B.CHUNK_BUCKETS)
+    assert dec.specialized
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(8) as ex:
+        parts = list(ex.map(lambda k: synth.frames(name, 100_000, 2.5 + 0.1 * k, seed=91, block=k), range(13)))
+    llr = torch.from_numpy(np.concatenate([q.llr for q in parts])).cuda()
+    d_o = torch.from_numpy(np.concatenate([q.d_o for q in parts])).cuda()
+    if precision == "fix8":
+        q8 = torch.empty(llr.shape, dtype=torch.int8, device="cuda")
+        B.quantize_llr(llr, c.N, 4.0, q8)
+        llr = q8
+    whole = dec.decode(llr, d_o)[:3]
+    outs = [dec.decode(llr[k:k + chunk].contiguous(), d_o[k:k + chunk].contiguous())[:3] for k in range(0, F, chunk)]
+    torch.cuda.synchronize()
+    for j in range(3):
+        assert torch.equal(whole[j], torch.cat([o[j] for o in outs])), j
+    assert int(whole[1].min()) >= 1
 
 
 @pytest.mark.parametrize("name,rows,per,grid,precision", [
