@@ -81,10 +81,10 @@ FIX_SCALE = 4.0
 # and of the generator functions that write its row function); any other build
 # reports traffic null.
 TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written, family, source hash)
-    "spec_bch127_64_m72_b9": (522.72, 87.02, "one_wave", "88a5df35fd8d7ebd"),
-    "spec_bch127_99_m33_b9": (521.95, 88.21, "one_wave", "88a5df35fd8d7ebd"),
-    "spec_bch127_64_m72_b9_fix8_pk16": (135.85, 82.50, "pk16", "0ce47e9984fbfdc1"),
-    "spec_bch127_99_m33_b9_fix8_pk16": (135.48, 83.81, "pk16", "0ce47e9984fbfdc1"),
+    "spec_bch127_64_m72_b9": (532.46, 201.30, "one_wave", "83400184c2c8e111"),
+    "spec_bch127_99_m33_b9": (538.16, 245.02, "one_wave", "83400184c2c8e111"),
+    "spec_bch127_64_m72_b9_fix8_pk16": (135.84, 83.98, "pk16", "abe1b3c305b92cea"),
+    "spec_bch127_99_m33_b9_fix8_pk16": (135.61, 82.37, "pk16", "abe1b3c305b92cea"),
 }
 KERNEL_FAMILIES = {
     "one_wave": (["csrc/nms_spec_fp32.inc", "csrc/nms_spec_rot.inc", "csrc/nms_spec_cursor.inc"],
