@@ -247,7 +247,7 @@ def make_decoder(args, B, code, pcm, name, rows, prec):
     precision = B.FIX8 if prec == "fix8" else B.FP32
     flags = (B.FORCE_GENERIC if args.generic else 0) | (B.PACKED16 if args.packed16 and prec == "fix8" else 0)
     flags |= B.CHUNK_BUCKETS if getattr(args, "chunk_buckets", False) else 0
-    path = getattr(args, "mixed_path", "auto")
+    path = getattr(args, "mixed_path", "fused")
     flags |= {"per-code": B.NO_MIXED_KERNEL, "fused": B.MIXED_KERNEL}.get(path, 0)
     alpha = workload_alpha(args, name, rows)
     if args.tuned and not args.generic:
@@ -767,9 +767,9 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="capture each launch of the step in a HIP graph once and replay it in the timed loop")
     ap.add_argument("--write-alpha", action="store_true", help="alpha workload: cache the results in tuning.json")
-    ap.add_argument("--mixed-path", default="auto", choices=["auto", "fused", "per-code"],
-                    help="mixed workload: the library's choice by batch size, the mixed-code kernel (one "
-                         "launch) or one launch per code")
+    ap.add_argument("--mixed-path", default="fused", choices=["auto", "fused", "per-code"],
+                    help="mixed workload: the mixed-code kernel (one launch, the workload's definition), "
+                         "the library's choice by batch size, or one launch per code")
     ap.add_argument("--mix-probs", default="", help="mixed workload: per-code frame probabilities, comma-separated")
     ap.add_argument("--requests", type=int, default=3000, help="requests of the serving workload")
     ap.add_argument("--osd", default="device", choices=["device", "host"], help="serving: where OSD-2 runs")

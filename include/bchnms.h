@@ -254,8 +254,9 @@ int bch_decoder_set_tuning(bch_decoder dec, int waves_per_cu);
  * pattern of one launch for a mixed batch); otherwise one prepass and one
  * persistent kernel per code.  The size limit is where the two paths cross
  * over: one launch saves the per-code launch tails, which dominate small
- * batches, while each code's own kernel holds fewer registers (the 63-bit
- * codes' kernels run three waves per SIMD, the mixed kernel one).  No host synchronisation, no memset: the call
+ * batches, while at large batches each code's own kernel is faster (the
+ * 63-bit codes' kernels run three waves per SIMD, the mixed kernel one, and
+ * large fixed-point calls take the packed 16-bit kernels).  No host synchronisation, no memset: the call
  * can be captured in a HIP graph and replayed.  Per-frame results do not
  * depend on the mix or the path: each frame decodes exactly as alone.
  */

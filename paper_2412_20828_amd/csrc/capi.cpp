@@ -228,7 +228,6 @@ static int mixed_fused(const bch::MixKernel *k, const bch_decoder *decs, int n_c
         L.alpha[c] = d->prm.alpha;
         L.max_iter[c] = d->prm.max_iter;
         L.weight[c] = (float)(9 * d->E);
-        L.two_slots[c] = d->N <= 64 ? 1 : 0;
     }
     BucketWs w = bucket_ws_carve(workspace, F, nb);
     hipError_t e = launch_bucketing_mixed(d_o, code_idx, n_codes, dps, F, w, stream);

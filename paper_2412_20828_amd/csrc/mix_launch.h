@@ -28,7 +28,6 @@ struct MixLaunch {
     float alpha[MIX_MAXC];
     int max_iter[MIX_MAXC];
     float weight[MIX_MAXC];   // work of one frame-iteration, for the start split
-    int two_slots[MIX_MAXC];  // 1: code of length 63, two frames per lane
 };
 
 }  // namespace bch

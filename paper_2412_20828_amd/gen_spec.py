@@ -66,9 +66,8 @@ MIXES = [
 ]
 # rows whose min searches interleave in the one-wave kernels: one with the
 # triple search (its steps hold two independent triples); two with the
-# entry-by-entry chain of the mixed-code kernel, whose dual-frame length-63
-# path keeps that kernel at the register limit (the triple search's extra live
-# values spill there and measured slower)
+# entry-by-entry chain that the length-127 codes of the mixed-code kernels
+# keep (the triple search's extra live values spill there and measured slower)
 ILP_ROWS = 1
 MIX_ILP_ROWS = 2
 
@@ -372,57 +371,12 @@ def body_source_fix8(H: np.ndarray, accumulate: bool = False) -> str:
     return "\n".join(out)
 
 
-def body_source_dual(H: np.ndarray, fix8: bool = False) -> str:
-    """The accumulating row function of the 32-bit decoders for two frames at
-    once (A0, S0 -> T0 and A1, S1 -> T1): per row both frames' min1/min2
-    chains and c2v selections interleaved step by step, each frame's
-    arithmetic exactly that of body_source(H, accumulate=True) (or
-    body_source_fix8), in the same row order."""
-    M, N = H.shape
-    out = [_MED3U, "__device__ __forceinline__ void body2(const float *__restrict__ A0, "
-           "const uint32_t *__restrict__ S0, float *__restrict__ T0, const float *__restrict__ A1, "
-           "const uint32_t *__restrict__ S1, float *__restrict__ T1)", "{"]
-    for j in range(M):
-        cols = [int(c) for c in np.nonzero(H[j])[0]]
-        masks = _sign_masks(cols, N)
-        out.append("    { // row %d" % j)
-        for f in (0, 1):
-            out.append("        const float sg%d = __uint_as_float(0x3f800000u | ((%s) << 31));"
-                       % (f, _parity("S%d" % f, masks)))
-        steps = [_min_steps(cols, "_%d" % f, lambda c, f=f: "__float_as_uint(A%d[%d])" % (f, c), tree=False)
-                 for f in (0, 1)]
-        for k in range(len(steps[0])):
-            for f in (0, 1):
-                out += ["        " + x for x in steps[f][k]]
-        for f in (0, 1):
-            out.append("        const float m1_%d = __uint_as_float(u1_%d), m2_%d = __uint_as_float(u2_%d);"
-                       % (f, f, f, f))
-            if fix8:
-                out.append("        const float q1_%d = floorf(__builtin_fmaf(m1_%d, 0.75f, 0.5f)), "
-                           "q2_%d = floorf(__builtin_fmaf(m2_%d, 0.75f, 0.5f));" % (f, f, f, f))
-                out.append("        const float K_%d = __builtin_fmaf(m1_%d, 128.0f, q2_%d);" % (f, f, f))
-            else:
-                out.append("        const float P_%d = m1_%d + m2_%d;" % (f, f, f))
-        for c in cols:
-            for f in (0, 1):
-                if fix8:
-                    mag = "__builtin_amdgcn_fmed3f(q1_%d, q2_%d, __builtin_fmaf(A%d[%d], -128.0f, K_%d))" % (
-                        f, f, f, c, f)
-                else:
-                    mag = "__builtin_amdgcn_fmed3f(m1_%d, m2_%d, P_%d - A%d[%d])" % (f, f, f, f, c)
-                out.append("        T%d[%d] = __builtin_fmaf(sg%d, %s, T%d[%d]);" % (f, c, f, mag, f, c))
-        # rows stay in order: no work is hoisted across a row, which keeps the
-        # live values of two frames within one wave's registers
-        out.append("        __builtin_amdgcn_sched_barrier(0);")
-        out.append("    }")
-    out.append("}")
-    return "\n".join(out)
-
-
 def mixed_source(ns, parts, prec, out_dir):
-    """Source of one mixed-code kernel: each code's row function(s) and
-    syndrome test in a namespace of its own, a traits struct per code, and the
-    template.  parts: [(code name, H, Hstd)]."""
+    """Source of one mixed-code kernel: each code's row function and syndrome
+    test in a namespace of its own, a traits struct per code, and the
+    template.  parts: [(code name, H, Hstd)].  Length-63 codes take the
+    triple min1/min2 search, length-127 codes the chain of two interleaved
+    rows (see MIX_ILP_ROWS)."""
     lines = ['#include "mix_launch.h"', "#define SPEC_FIX8 %d" % prec, "#include <hip/hip_runtime.h>",
              "#include <cstdint>", "namespace bch {", "namespace %s {" % ns]
     traits, cases = [], []
@@ -434,15 +388,11 @@ def mixed_source(ns, parts, prec, out_dir):
             if N > 64:
                 fh.write(body_source_ilp(H, fix8=bool(prec), group=MIX_ILP_ROWS, tree=False))
             else:
-                fh.write(body_source_dual(H, fix8=bool(prec)))
+                fh.write(body_source_ilp(H, fix8=bool(prec), group=1, tree=True))
             fh.write("\n\n" + syndrome_source(Hs) + "\n")
         lines += ["namespace c%d {" % k, '#include "%s"' % os.path.basename(body_path), "}"]
-        if N > 64:
-            fn = ("    __device__ static __forceinline__ void body(const float *A, const uint32_t *S, float *T) "
-                  "{ c%d::body(A, S, T); }" % k)
-        else:
-            fn = ("    __device__ static __forceinline__ void body2(const float *A0, const uint32_t *S0, float *T0, "
-                  "const float *A1, const uint32_t *S1, float *T1) { c%d::body2(A0, S0, T0, A1, S1, T1); }" % k)
+        fn = ("    __device__ static __forceinline__ void body(const float *A, const uint32_t *S, float *T) "
+              "{ c%d::body(A, S, T); }" % k)
         traits += ["struct T%d {" % k, "    static constexpr int N = %d;" % N, fn,
                    "    __device__ static __forceinline__ bool syndrome(const uint64_t *w) "
                    "{ return c%d::syndrome_zero(w); }" % k, "};"]
