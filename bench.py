@@ -650,20 +650,25 @@ def run_experiment(args):
             code = B.Code(d.m, d.prim, d.t)
             ho = B.Pcm.build(code, target_rows=rows_h, seed=1)
             hs = B.Pcm.standard(code)
-            cfgs = [("plain NMS, H_std (%dx63), 1 branch, extrinsic" % hs.M, hs, 1, B.MODE_EXTRINSIC),
-                    ("NMS on H_o, 1 branch, restart", ho, 1, B.MODE_RESTART),
-                    ("enhanced NMS, 3 branches", ho, 3, B.MODE_RESTART),
-                    ("enhanced NMS, 9 branches", ho, 9, B.MODE_RESTART)]
+            cfgs = [("plain NMS, H_std (%dx63), 1 branch, extrinsic" % hs.M, hs, 1, B.MODE_EXTRINSIC, 0),
+                    ("plain NMS, H_std (%dx63), 1 branch, extrinsic, generic kernel" % hs.M, hs, 1,
+                     B.MODE_EXTRINSIC, B.FORCE_GENERIC),
+                    ("NMS on H_o, 1 branch, restart", ho, 1, B.MODE_RESTART, 0),
+                    ("enhanced NMS, 3 branches", ho, 3, B.MODE_RESTART, 0),
+                    ("enhanced NMS, 9 branches", ho, 9, B.MODE_RESTART, 0)]
             for pi, e in enumerate(points):
                 llr_h, cw, d_o_h = gen_point(name, F, e, seed=7000 + 10 * ci + pi)
                 truth = pack(cw)
                 llr, d_o = torch.from_numpy(llr_h).to(dev), torch.from_numpy(d_o_h).to(dev)
-                for label, pcm, nb, mode in cfgs:
-                    dec = B.Decoder(code, pcm, n_branches=nb, mode=mode, alpha=0.75, max_iter=8)
+                for label, pcm, nb, mode, flags in cfgs:
+                    dec = B.Decoder(code, pcm, n_branches=nb, mode=mode, alpha=0.75, max_iter=8, flags=flags)
                     w, it, fl, sec = timed_decode(dec, llr, d_o, torch, reps=1)
-                    rows.append({"code": name, "ebn0": e, "config": label, "specialised_kernel": dec.specialized,
+                    ops = float(it.astype(np.int64).sum()) * alg_ops_per_iteration(code.N, code.K, pcm.M, pcm.E,
+                                                                                    nb, mode)
+                    rows.append({"code": name, "ebn0": e, "config": label, "kernel": dec.kernel_name(F),
                                  "fer": float((w != truth[:, :w.shape[1]]).any(1).mean()),
-                                 "avg_iters": float(it.mean()), "frames_per_s": F / sec})
+                                 "avg_iters": float(it.mean()), "frames_per_s": F / sec,
+                                 "valu_frac": ops / sec / VALU_PEAK_OPS})
         out.update({"workload": "ablation", "config": {"workload": "branch-count ablation, alpha 0.75, I_m 8, "
                                                                   "%d frames per point" % F}})
     out["rows"] = rows

@@ -14,9 +14,10 @@ import os
 
 import numpy as np
 
-# (code name, target rows of H_o, n_branches, mode, precision (0 FP32, 1 FIX8),
-#  waves per CU of the persistent grid[, variant: 1 = packed 16-bit fixed point,
-#  2 = three waves per 64 frames for N = 127, the kernel for small batches])
+# (code name, target rows of H_o (0: the standard matrix), n_branches, mode
+#  (1 restart, 3 extrinsic messages), precision (0 FP32, 1 FIX8), waves per CU
+#  of the persistent grid[, variant: 1 = packed 16-bit fixed point, 2 = three
+#  waves per 64 frames for N = 127, the kernel for small batches])
 SPECS = [
     ("bch63_45", 33, 9, 1, 0, 12),
     ("bch63_36", 122, 9, 1, 0, 12),
@@ -55,6 +56,11 @@ SPECS = [
     ("bch63_36", 122, 3, 1, 0, 8),
     ("bch63_45", 33, 1, 1, 0, 5),
     ("bch63_36", 122, 1, 1, 0, 4),
+    # plain NMS with extrinsic messages on the standard matrices (rows 0):
+    # the small configuration of the length-63 codes and the ablation's
+    # baseline
+    ("bch63_36", 0, 1, 3, 0, 8),
+    ("bch63_45", 0, 1, 3, 0, 8),
 ]
 # mixed-code kernels: one persistent launch over frames of these codes, code k
 # of a mixed call being the k-th matrix here: the mixed workload's codes (FP32
@@ -70,6 +76,14 @@ MIXES = [
 # keep (the triple search's extra live values spill there and measured slower)
 ILP_ROWS = 1
 MIX_ILP_ROWS = 2
+# edges between scheduling barriers in the extrinsic-message row function
+EXT_GROUP = 4
+# frames a wave of the one- and three-branch kernels asks its cursor for at
+# least: they stop frames nearly every iteration, at rates where one cursor
+# atomic per iteration of every wave limits them.  The nine-branch kernels
+# take exactly their idle slots (measured: a reserve per workgroup of the
+# grouped N = 63 kernels gained nothing)
+RESERVE = 64
 
 CODE_DEFS = {
     "bch63_36": (6, 0b1000011, 5),
@@ -95,6 +109,9 @@ def _matrices(lib, name, rows):
     N, K = N.value, K.value
     Hs = np.zeros((N - K, N), np.uint8)
     lib.bch_code_export(code, None, None, Hs.ctypes.data_as(ctypes.c_void_p))
+    if rows == 0:  # the standard matrix
+        lib.bch_code_destroy(code)
+        return Hs.copy(), Hs
     p = _PcmParams(1, 2, rows, 4, 1, 200, 10.0)
     pcm = ctypes.c_void_p()
     assert lib.bch_build_pcm(code, ctypes.byref(p), ctypes.byref(pcm)) == 0
@@ -406,6 +423,92 @@ def mixed_source(ns, parts, prec, out_dir):
     return src_path
 
 
+def body_source_ext(H: np.ndarray) -> str:
+    """Row function of the plain NMS decoder with extrinsic messages
+    (nms_spec_ext.inc), in two passes over the rows.  Pass one: for every
+    row, v = Y[c] - c2v_old on each edge (the old message rebuilt from the
+    row's compressed state), min1/min2 of |v| (the triple search on the bit
+    patterns) and the sign parity, and the new compressed state: RA = alpha
+    min1, RB = alpha min2, RW = the new messages' sign bits (sign parity x
+    sgn(v); the row's i-th edge of w at bit w - 1 - i, as v_alignbit shifts
+    them in) with an argmin's edge index + 1 in bits 24-31.  Pass two: every
+    row's new message, alpha min2 at the argmin and alpha min1 elsewhere with
+    its sign bit, added into T[c], rows in ascending order.  Y is dead once
+    pass one ends, so the sums T take its registers instead of living beside
+    it.  Ties at min1 give min2 = min1, so every tied edge gets the same
+    magnitude whichever is called the argmin (the last one here).  The sign
+    of a zero |v| decides only messages of magnitude zero."""
+    M, N = H.shape
+    out = [_MED3U, "__device__ __forceinline__ void body_ext(const float *__restrict__ Y, float *__restrict__ T, "
+           "float *RA, float *RB, uint32_t *RW, float alpha)", "{"]
+    for j in range(M):
+        cols = [int(c) for c in np.nonzero(H[j])[0]]
+        w = len(cols)
+        if w > 24 or N > 255:
+            raise ValueError("the compressed state holds rows of at most 24 entries")
+        out.append("    { // row %d" % j)
+        out += _ext_messages(j, cols, "const float v%d = Y[%d] - ")
+        vals = ["(__float_as_uint(v%d) & 0x7fffffffu)" % i for i in range(w)]
+        for st in _min_steps(list(range(w)), "", lambda i: vals[i]):
+            out += ["        " + x for x in st]
+        # one v_alignbit per edge: s = (s << 1) | sign of v
+        out.append("        uint32_t s = 0u;")
+        for i in range(w):
+            out.append("        s = __builtin_amdgcn_alignbit(s, __float_as_uint(v%d), 31);" % i)
+        out.append("        const uint32_t par = __builtin_popcount(s) & 1u;")
+        out.append("        const float am1 = alpha * __uint_as_float(u1), am2 = alpha * __uint_as_float(u2);")
+        out.append("        uint32_t kn = 0u;")
+        for i in range(w):
+            out.append("        kn = (__float_as_uint(v%d) & 0x7fffffffu) == u1 ? %du : kn;" % (i, i + 1))
+        out.append("        RA[%d] = am1;" % j)
+        out.append("        RB[%d] = am2;" % j)
+        out.append("        RW[%d] = (kn << 24) | (s ^ (par ? 0x%xu : 0u));" % (j, (1 << w) - 1))
+        # rows in order: every row's v depends only on the inputs, and hoisting
+        # them across rows would keep dozens of rows' values live at once
+        out.append("        __builtin_amdgcn_sched_barrier(0);")
+        out.append("    }")
+    for j in range(M):
+        cols = [int(c) for c in np.nonzero(H[j])[0]]
+        out.append("    { // row %d, new messages" % j)
+        out += _ext_messages(j, cols, "T[%d] += ", idx=False, after=M - 1)
+        out.append("        __builtin_amdgcn_sched_barrier(0);")
+        out.append("    }")
+    out.append("}")
+    return "\n".join(out)
+
+
+def _ext_messages(j, cols, lhs, idx=True, after=None):
+    """Statements that rebuild row j's messages from its compressed state
+    (RA, RB, RW) and apply lhs to each: the message of the row's i-th edge
+    (column c) is RB at the argmin, RA elsewhere, with bit w - 1 - i of RW
+    as its sign (w edges).  With after = r, the rebuild takes RW[r] and RB[r] as inputs of its
+    opaque step, so that it cannot be placed before row r's state is final (the
+    compiler otherwise starts the second pass's first rows ahead of the
+    first pass's last ones, with both passes' values live at once)."""
+    out = ["        const float a = RA[%d], b = RB[%d];" % (j, j),
+           # sw opaque: otherwise the compiler folds each edge's shift and
+           # mask of it into the loop's phi and carries the row's sign bits in
+           # as many registers from one iteration to the next instead of one
+           # word; k opaque: compared with inline constants, not folded into
+           # byte-select compares whose constant operands it would keep in
+           # registers
+           "        uint32_t sw = RW[%d], k;" % j,
+           ('        __asm__("" : "+v"(sw));' if after is None else
+            '        __asm__("" : "+v"(sw) : "v"(RW[%d]), "v"(RB[%d]));' % (after, after)),
+           '        __asm__("v_lshrrev_b32 %0, 24, %1" : "=v"(k) : "v"(sw));']
+    w = len(cols)
+    for i, c in enumerate(cols):
+        head = (lhs % (i, c)) if idx else (lhs % c)
+        out.append("        %s__uint_as_float(__float_as_uint(k == %du ? b : a) | ((sw << %d) & 0x80000000u));"
+                   % (head, i + 1, 32 - w + i))
+        # the lane masks of the compares are consumed at once: scheduling
+        # barriers every few edges keep the compiler from computing all of a
+        # row's compares first and spilling their masks
+        if i % EXT_GROUP == EXT_GROUP - 1:
+            out.append("        __builtin_amdgcn_sched_barrier(0);")
+    return out
+
+
 def body_source_pk16(H: np.ndarray, B: int) -> str:
     """Row function of the packed 16-bit fixed-point decoder: A, T hold two
     frames per register (v2s), SL / SH their sign bits.  Adds s_j * mag_j(i)
@@ -496,8 +599,8 @@ def generate(stage1_lib: str, out_dir: str):
             mats[(name, rows)] = _matrices(lib, name, rows)
         H, Hs = mats[(name, rows)]
         M, N = H.shape
-        ns = "spec_%s_m%d_b%d%s%s" % (name, M, B, "_fix8" if prec else "",
-                                       {0: "", 1: "_pk16", 2: "_grp"}[variant])
+        ns = "spec_%s_m%d_b%d%s%s%s" % (name, M, B, "_fix8" if prec else "",
+                                         {0: "", 1: "_pk16", 2: "_grp"}[variant], "_ext" if mode == 3 else "")
         body_path = os.path.join(out_dir, ns + "_body.inc")
         regacc = 1 if B > 1 else 0
         pk16 = 1 if prec and regacc and variant == 1 else 0
@@ -508,9 +611,16 @@ def generate(stage1_lib: str, out_dir: str):
             raise ValueError("the packed variant needs fixed point and 3 or 9 branches")
         if variant == 2 and not (group and N > 64):
             raise ValueError("the small-batch variant is for nine branches and N = 127")
+        ext = mode == 3
+        if ext and not (B == 1 and prec == 0 and variant == 0):
+            raise ValueError("the extrinsic-message kernel is one-branch FP32")
+        if not ext and mode != 1:
+            raise ValueError("specialised kernels: restart mode, or one-branch extrinsic messages")
         with open(body_path, "w") as fh:
-            fh.write("// generated: %s, H_o %d x %d, %d edges\n" % (name, M, N, int(H.sum())))
-            if pk16:
+            fh.write("// generated: %s, H %d x %d, %d edges\n" % (name, M, N, int(H.sum())))
+            if ext:
+                fh.write(body_source_ext(H))
+            elif pk16:
                 fh.write(body_source_pk16(H, B))
             else:
                 if regacc and N > 64:
@@ -528,7 +638,11 @@ def generate(stage1_lib: str, out_dir: str):
             fh.write('#define SPEC_BODY "%s"\n' % os.path.basename(body_path))
             if group and N > 64:
                 fh.write("#define SPEC_WAVES_PER_SIMD 1\n")
-            fh.write('#include "%s"\n' % ("nms_spec_pk16.inc" if pk16 else
+            if ext:
+                fh.write("#define SPEC_M %d\n" % M)
+            if not (pk16 or group):
+                fh.write("#define SPEC_RESERVE %d\n" % (RESERVE if ext or B < 9 else 0))
+            fh.write('#include "%s"\n' % ("nms_spec_ext.inc" if ext else "nms_spec_pk16.inc" if pk16 else
                                            "nms_spec_group.inc" if group else "nms_spec_fp32.inc"))
         srcs.append(src_path)
         decls.append("namespace %s { hipError_t launch(const SpecLaunch &, int, int, hipStream_t); }" % ns)

@@ -322,6 +322,45 @@ def test_plain_nms_standard_matrix_config(B):
     assert abs(err_g - err_o) <= ties
 
 
+@pytest.mark.parametrize("generic", [False, True])
+@pytest.mark.parametrize("name,ebn0,alpha,kind", [("bch63_36", 3.0, 0.75, None), ("bch63_45", 3.5, 0.75, None),
+                                                  ("bch63_36", 2.0, 1.0, None), ("bch63_45", 2.5, 0.6, None),
+                                                  ("bch63_36", 3.0, 0.75, "equal"), ("bch63_45", 3.0, 0.75, "mixed")])
+def test_plain_nms_extrinsic_kernel(B, name, ebn0, alpha, kind, generic):
+    """The specialised kernel of plain flooding NMS with extrinsic messages
+    (one branch, standard matrix) and the generic kernel it replaces, on
+    several waves with a ragged tail, at three values of alpha and on
+    adversarial frames (equal magnitudes, -0.0 and subnormals): the parity bar
+    of the edge-memory modes against the FP64 oracle."""
+    N, ld, F = 63, 64, 64 * 5 + 23
+    x = adversarial_frames(N, ld, F, 300, kind) if kind else None
+    fr, g, o, dec = run_pair(B, name, 0, F, ebn0, 41, 1, oracle.R3, 12, alpha=alpha,
+                             flags=B.FORCE_GENERIC if generic else 0, llr_h=x)
+    rows = {"bch63_36": 27, "bch63_45": 18}[name]
+    assert dec.kernel_name(F) == ("generic" if generic else "spec_%s_m%d_b1_ext" % (name, rows))
+    compare_with_oracle(*g, *o, max_tie_frac=1.0 if kind else 0.02)
+
+
+def test_plain_nms_extrinsic_kernel_matches_generic(B):
+    """At 20,000 frames of BCH(63,36) at 2.5 dB (many frames run all 12
+    iterations), the specialised and generic kernels take the same decisions
+    except on frames whose posteriors pass within FP32 rounding of zero: at
+    most 0.5% differ, and the frame error rates agree within that."""
+    c, p = lib_objects(B, "bch63_36", 0)
+    fr = synth.frames("bch63_36", 20000, 2.5, seed=43)
+    llr = torch.from_numpy(fr.llr).cuda()
+    out = []
+    for flags in (0, B.FORCE_GENERIC):
+        dec = B.Decoder(c, p, n_branches=1, mode=B.MODE_EXTRINSIC, max_iter=12, flags=flags)
+        bits, iters, _, _ = dec.decode(llr)
+        torch.cuda.synchronize()
+        out.append((B.unpack_bits(bits.cpu().numpy().view(np.uint64), c.N), iters.cpu().numpy()))
+    diff = (out[0][0] != out[1][0]).any(1) | (out[0][1] != out[1][1])
+    assert diff.mean() <= 0.005
+    errs = [int((w != fr.codewords).any(1).sum()) for w, _ in out]
+    assert abs(errs[0] - errs[1]) <= int(diff.sum())
+
+
 @pytest.mark.parametrize("name,alpha,flags", [("bch63_45", 0.55, 0), ("bch63_45", 1.0, 0), ("bch63_36", 0.55, 0),
                                               ("bch127_64", 1.0, "SMALL_NEVER"), ("bch127_64", 1.0, "SMALL_ALWAYS"),
                                               ("bch127_99", 1.0, "SMALL_NEVER"), ("bch127_99", 0.6, "SMALL_ALWAYS")])
@@ -423,6 +462,29 @@ def test_one_and_three_branch_variants(B, name, nb, generic):
                              flags=B.FORCE_GENERIC if generic else 0)
     assert dec.specialized == (not generic)
     compare_with_oracle(*g, *o, onestep=dec.onestep)
+
+
+@pytest.mark.parametrize("name,rows,nb,mode", [("bch63_36", 0, 1, "MODE_EXTRINSIC"), ("bch63_45", 0, 1, "MODE_EXTRINSIC"),
+                                               ("bch63_45", 33, 1, "MODE_RESTART"), ("bch63_36", 122, 3, "MODE_RESTART")])
+def test_reserved_handout_covers_every_frame(B, name, rows, nb, mode):
+    """The one- and three-branch kernels take frames with a private reserve
+    of 64 slots per wave while their bucket is far from dry.  A 300,000-frame
+    call (many reserves per wave, then exact grabs near the end) must decode
+    every frame exactly as calls of 20,000 frames do, where the reserve rarely
+    engages: nothing lost, repeated or decoded twice."""
+    F, chunk = 300_000, 20_000
+    c, p = lib_objects(B, name, rows)
+    dec = B.Decoder(c, p, n_branches=nb, mode=getattr(B, mode), alpha=0.75, max_iter=8)
+    assert dec.specialized
+    fr = synth.frames(name, F, 2.5, seed=97)
+    llr = torch.from_numpy(fr.llr).cuda()
+    d_o = torch.from_numpy(fr.d_o).cuda()
+    whole = dec.decode(llr, d_o)[:3]
+    outs = [dec.decode(llr[k:k + chunk].contiguous(), d_o[k:k + chunk].contiguous())[:3] for k in range(0, F, chunk)]
+    torch.cuda.synchronize()
+    for j in range(3):
+        assert torch.equal(whole[j], torch.cat([o[j] for o in outs])), j
+    assert int(whole[1].min()) >= 1
 
 
 def test_edge_cases(B):
@@ -714,7 +776,8 @@ def test_mixed_batch_against_oracle(B):
 def test_mixed_batch_rejections(B):
     objs, decs, mf, llr = mixed_setup(B, 0, 64, seed=3)
     c, p = lib_objects(B, "bch63_45", 0)
-    generic = B.Decoder(c, p, n_branches=1, mode=B.MODE_EXTRINSIC, max_iter=4)
+    generic = B.Decoder(c, p, n_branches=3, mode=B.MODE_EXTRINSIC, max_iter=4)
+    assert not generic.specialized
     ci = torch.from_numpy(mf.code_idx).cuda()
     d_o = torch.from_numpy(mf.d_o).cuda()
     with pytest.raises(B.BchError):
