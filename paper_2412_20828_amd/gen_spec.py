@@ -76,6 +76,8 @@ MIXES = [
 # keep (the triple search's extra live values spill there and measured slower)
 ILP_ROWS = 1
 MIX_ILP_ROWS = 2
+# entries whose update steps the packed 16-bit row function interleaves
+PK16_GROUP = 4
 # edges between scheduling barriers in the extrinsic-message row function
 EXT_GROUP = 4
 # frames a wave of the one- and three-branch kernels asks its cursor for at
@@ -555,8 +557,15 @@ def body_source_pk16(H: np.ndarray, B: int) -> str:
         out.append("        const v2s m1 = vmin(x1, y1), m2 = vmin(vmax(x1, y1), vmin(x2, y2));")
         out.append("        const v2s q1 = (m1 * (v2s)3 + (v2s)2) >> (v2s)2, q2 = (m2 * (v2s)3 + (v2s)2) >> (v2s)2;")
         out.append("        const v2s K = m1 * (v2s)100 + q2;")
-        for c in cols:
-            out.append("        T[%d] = sg * vmax(q1, vmin(q2, A[%d] * (v2s)(-100) + K)) + T[%d];" % (c, c, c))
+        # the four dependent steps of an entry's update, emitted a group of
+        # entries at a time: a packed 16-bit result read by the next
+        # instruction costs a wait state, which independent entries fill
+        for g0 in range(0, len(cols), PK16_GROUP):
+            grp = cols[g0:g0 + PK16_GROUP]
+            out.append("        " + " ".join("v2s t%d = A[%d] * (v2s)(-100) + K;" % (c, c) for c in grp))
+            out.append("        " + " ".join("t%d = vmin(q2, t%d);" % (c, c) for c in grp))
+            out.append("        " + " ".join("t%d = vmax(q1, t%d);" % (c, c) for c in grp))
+            out.append("        " + " ".join("T[%d] = sg * t%d + T[%d];" % (c, c, c) for c in grp))
         out.append("    }")
     out.append("}")
     return "\n".join(out)
