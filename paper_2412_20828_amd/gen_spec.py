@@ -76,6 +76,12 @@ MIXES = [
 # keep (the triple search's extra live values spill there and measured slower)
 ILP_ROWS = 1
 MIX_ILP_ROWS = 2
+# nine-branch kernels of the length-127 codes (one wave per SIMD) compile the
+# three cyclic shifts of a permutation type as three row functions, each on
+# the matrix with its columns rotated by s d_p: a type then gathers its input
+# once instead of three times, and its sums need no register rotation between
+# the shifts
+FOLD_SHIFTS = True
 # entries whose update steps the packed 16-bit row function interleaves
 PK16_GROUP = 4
 # edges between scheduling barriers in the extrinsic-message row function
@@ -163,9 +169,7 @@ _MED3U = """__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, ui
 }
 __device__ __forceinline__ uint32_t med3i(uint32_t a, uint32_t b, uint32_t c)
 {
-    uint32_t r;
-    __asm__("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
+    return __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(a), __uint_as_float(b), __uint_as_float(c)));
 }
 """
 
@@ -267,7 +271,8 @@ def _forward(cols):
     return out
 
 
-def body_source_ilp(H: np.ndarray, fix8: bool = False, group: int = 1, tree: bool = True) -> str:
+def body_source_ilp(H: np.ndarray, fix8: bool = False, group: int = 1, tree: bool = True,
+                    helpers: bool = True) -> str:
     """The row function (accumulating form, FP32 or fixed point) with
     independent work side by side, for kernels that run one wave per SIMD and
     so have no other wave to issue while an instruction waits for its
@@ -278,8 +283,8 @@ def body_source_ilp(H: np.ndarray, fix8: bool = False, group: int = 1, tree: boo
     time, pinned by scheduling barriers.  Every column is still updated by its
     rows in ascending order."""
     M, N = H.shape
-    out = [_MED3U, "__device__ __forceinline__ void body(const float *__restrict__ A, "
-           "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
+    out = ([_MED3U] if helpers else []) + ["__device__ __forceinline__ void body(const float *__restrict__ A, "
+                                           "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
     for j0 in range(0, M, group):
         rows = list(range(j0, min(M, j0 + group)))
         out.append("    { // rows %s" % ", ".join(map(str, rows)))
@@ -571,6 +576,25 @@ def body_source_pk16(H: np.ndarray, B: int) -> str:
     return "\n".join(out)
 
 
+def shift_matrices(H: np.ndarray, dp: int, ns: int = 3):
+    """The matrix of each cyclic shift s d_p (s < ns) in the frame of shift 0:
+    the row function of branch s reads entry c of the shifted input at index
+    (c - s d_p) mod N of the shift-0 input, so its matrix is H with its
+    columns rotated left by s d_p.  The rows and their order are H's."""
+    return [np.roll(H, -s * dp, axis=1) for s in range(ns)]
+
+
+def folded_body_source(H: np.ndarray, dp: int, emit) -> str:
+    """Three row functions f0::body, f1::body, f2::body, one per cyclic shift
+    (see shift_matrices); emit(H_s) returns the source of one."""
+    out = []
+    for s, Hs in enumerate(shift_matrices(H, dp)):
+        out.append("namespace f%d {" % s)
+        out.append(emit(Hs))
+        out.append("}  // namespace f%d" % s)
+    return "\n".join(out)
+
+
 def syndrome_source(Hs: np.ndarray) -> str:
     Ms, N = Hs.shape
     W64 = (N + 63) // 64
@@ -621,6 +645,9 @@ def generate(stage1_lib: str, out_dir: str):
         if variant == 2 and not (group and N > 64):
             raise ValueError("the small-batch variant is for nine branches and N = 127")
         ext = mode == 3
+        # the one-wave nine-branch kernels of the length-127 codes
+        fold = FOLD_SHIFTS and regacc and B == 9 and N > 64 and not group and not ext
+        dp = {63: 21, 127: 42}.get(N, N // 3)
         if ext and not (B == 1 and prec == 0 and variant == 0):
             raise ValueError("the extrinsic-message kernel is one-branch FP32")
         if not ext and mode != 1:
@@ -629,10 +656,16 @@ def generate(stage1_lib: str, out_dir: str):
             fh.write("// generated: %s, H %d x %d, %d edges\n" % (name, M, N, int(H.sum())))
             if ext:
                 fh.write(body_source_ext(H))
+            elif pk16 and fold:
+                fh.write(folded_body_source(H, dp, lambda Hs: body_source_pk16(Hs, B)))
             elif pk16:
                 fh.write(body_source_pk16(H, B))
             else:
-                if regacc and N > 64:
+                if fold:
+                    fh.write(_MED3U + "\n" + folded_body_source(
+                        H, dp, lambda Hs: body_source_ilp(Hs, fix8=bool(prec), group=ILP_ROWS, tree=True,
+                                                                helpers=False)))
+                elif regacc and N > 64:
                     fh.write(body_source_ilp(H, fix8=bool(prec), group=ILP_ROWS, tree=True))
                 else:
                     fh.write(body_source_fix8(H, regacc) if prec else body_source(H, regacc))
@@ -649,6 +682,8 @@ def generate(stage1_lib: str, out_dir: str):
                 fh.write("#define SPEC_WAVES_PER_SIMD 1\n")
             if ext:
                 fh.write("#define SPEC_M %d\n" % M)
+            if fold:
+                fh.write("#define SPEC_FOLD 1\n")
             if not (pk16 or group):
                 fh.write("#define SPEC_RESERVE %d\n" % (RESERVE if ext or B < 9 else 0))
             fh.write('#include "%s"\n' % ("nms_spec_ext.inc" if ext else "nms_spec_pk16.inc" if pk16 else
