@@ -76,11 +76,10 @@ MIXES = [
 # keep (the triple search's extra live values spill there and measured slower)
 ILP_ROWS = 1
 MIX_ILP_ROWS = 2
-# nine-branch kernels of the length-127 codes (one wave per SIMD) compile the
-# three cyclic shifts of a permutation type as three row functions, each on
-# the matrix with its columns rotated by s d_p: a type then gathers its input
-# once instead of three times, and its sums need no register rotation between
-# the shifts
+# nine-branch kernels compile the three cyclic shifts of a permutation type as
+# three row functions, each on the matrix with its columns rotated by s d_p: a
+# type then gathers its input once instead of three times, and its sums need
+# no register rotation between the shifts
 FOLD_SHIFTS = True
 # entries whose update steps the packed 16-bit row function interleaves
 PK16_GROUP = 4
@@ -645,8 +644,8 @@ def generate(stage1_lib: str, out_dir: str):
         if variant == 2 and not (group and N > 64):
             raise ValueError("the small-batch variant is for nine branches and N = 127")
         ext = mode == 3
-        # the one-wave nine-branch kernels of the length-127 codes
-        fold = FOLD_SHIFTS and regacc and B == 9 and N > 64 and not group and not ext
+        # the nine-branch kernels
+        fold = FOLD_SHIFTS and regacc and B == 9 and not ext
         dp = {63: 21, 127: 42}.get(N, N // 3)
         if ext and not (B == 1 and prec == 0 and variant == 0):
             raise ValueError("the extrinsic-message kernel is one-branch FP32")
@@ -661,10 +660,14 @@ def generate(stage1_lib: str, out_dir: str):
             elif pk16:
                 fh.write(body_source_pk16(H, B))
             else:
-                if fold:
+                if fold and N > 64:
                     fh.write(_MED3U + "\n" + folded_body_source(
                         H, dp, lambda Hs: body_source_ilp(Hs, fix8=bool(prec), group=ILP_ROWS, tree=True,
                                                                 helpers=False)))
+                elif fold:
+                    fh.write(_MED3U + "\n" + folded_body_source(
+                        H, dp, lambda Hs: (body_source_fix8(Hs, regacc) if prec else body_source(Hs, regacc))
+                        .replace(_MED3U, "")))
                 elif regacc and N > 64:
                     fh.write(body_source_ilp(H, fix8=bool(prec), group=ILP_ROWS, tree=True))
                 else:
