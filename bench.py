@@ -89,9 +89,10 @@ TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written, family, source hash)
 KERNEL_FAMILIES = {
     "one_wave": (["csrc/nms_spec_fp32.inc", "csrc/nms_spec_rot.inc", "csrc/nms_spec_cursor.inc"],
                  ["body_source_ilp", "_min_steps", "syndrome_source", "_sign_masks", "_parity", "_MED3U",
-                  "ILP_ROWS"]),
+                  "ILP_ROWS", "FOLD_SHIFTS", "folded_body_source", "shift_matrices"]),
     "pk16": (["csrc/nms_spec_pk16.inc", "csrc/nms_spec_rot.inc", "csrc/nms_spec_cursor.inc"],
-             ["body_source_pk16", "syndrome_source", "_parity"]),
+             ["body_source_pk16", "syndrome_source", "_parity", "PK16_GROUP", "FOLD_SHIFTS",
+              "folded_body_source", "shift_matrices"]),
 }
 
 
