@@ -81,15 +81,15 @@ FIX_SCALE = 4.0
 # and of the generator functions that write its row function); any other build
 # reports traffic null.
 TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written, family, source hash)
-    "spec_bch127_64_m72_b9": (532.46, 201.30, "one_wave", "83400184c2c8e111"),
-    "spec_bch127_99_m33_b9": (538.16, 245.02, "one_wave", "83400184c2c8e111"),
-    "spec_bch127_64_m72_b9_fix8_pk16": (135.84, 83.98, "pk16", "abe1b3c305b92cea"),
-    "spec_bch127_99_m33_b9_fix8_pk16": (135.61, 82.37, "pk16", "abe1b3c305b92cea"),
+    "spec_bch127_64_m72_b9": (534.17, 214.28, "one_wave", "98f84739218fa850"),
+    "spec_bch127_99_m33_b9": (537.87, 240.65, "one_wave", "98f84739218fa850"),
+    "spec_bch127_64_m72_b9_fix8_pk16": (135.96, 85.02, "pk16", "39901715f12b16f7"),
+    "spec_bch127_99_m33_b9_fix8_pk16": (135.66, 85.80, "pk16", "39901715f12b16f7"),
 }
 KERNEL_FAMILIES = {
     "one_wave": (["csrc/nms_spec_fp32.inc", "csrc/nms_spec_rot.inc", "csrc/nms_spec_cursor.inc"],
                  ["body_source_ilp", "_min_steps", "syndrome_source", "_sign_masks", "_parity", "_MED3U",
-                  "ILP_ROWS", "FOLD_SHIFTS", "folded_body_source", "shift_matrices"]),
+                  "ILP_ROWS", "FOLD_SHIFTS", "FOLD_EXCLUDE", "folded_body_source", "shift_matrices"]),
     "pk16": (["csrc/nms_spec_pk16.inc", "csrc/nms_spec_rot.inc", "csrc/nms_spec_cursor.inc"],
              ["body_source_pk16", "syndrome_source", "_parity", "PK16_GROUP", "FOLD_SHIFTS",
               "folded_body_source", "shift_matrices"]),
