@@ -102,3 +102,42 @@ def test_min_search_instruction_counts():
         return sum(len(re.findall(r"\b(min|max|med3[ui])\(", x)) - x.count("min(min(") for x in lines)
     assert count({"tree": False}) == 2 * 24 - 2
     assert count({}) == 8 * 24 // 6 - 1  # the first two triples merge with three, not four
+
+
+def _c2v_sums(H, Y):
+    """Per coordinate, the sum over the rows containing it of the signed
+    min-sum message (sign product of the row's other entries times their
+    least magnitude), in row order: what one row function adds into U."""
+    M, N = H.shape
+    U = np.zeros(N)
+    for r in range(M):
+        cols = np.nonzero(H[r])[0]
+        for c in cols:
+            others = [k for k in cols if k != c]
+            U[c] += np.prod(np.sign(Y[others])) * np.min(np.abs(Y[others]))
+    return U
+
+
+@pytest.mark.parametrize("N, dp", [(63, 21), (127, 42)])
+def test_shift_matrices_fold_a_type_onto_one_gather(N, dp):
+    """A nine-branch kernel runs shift s of permutation type p as the row
+    function of shift_matrices(H)[s] on the type's shift-0 input
+    B[k] = y[a (k - d_o)] and adds into U in B's frame.  That must equal the
+    branch itself, H on Y[i] = y[a (i - s d_p - d_o)], with its sums read
+    back through Y[i] = B[(i - s d_p) mod N]."""
+    rng = np.random.default_rng(3)
+    H = (rng.random((9, N)) < 0.2).astype(np.uint8)
+    H[:, 0] = 1
+    mats = gen_spec.shift_matrices(H, dp)
+    assert len(mats) == 3 and np.array_equal(mats[0], H)
+    for a in (1, 2, (N + 1) // 2):
+        y = rng.normal(size=N)
+        d_o = int(rng.integers(0, dp))
+        Bp = y[(a * (np.arange(N) - d_o)) % N]
+        folded = sum(_c2v_sums(Hs, Bp) for Hs in mats)
+        direct = np.zeros(N)
+        for s in range(3):
+            Y = y[(a * (np.arange(N) - s * dp - d_o)) % N]
+            U = _c2v_sums(H, Y)
+            direct[(np.arange(N) - s * dp) % N] += U  # entry i of the branch is B[(i - s d_p) mod N]
+        np.testing.assert_allclose(folded, direct, rtol=1e-12, atol=1e-12)
