@@ -76,6 +76,7 @@ MIXES = [
 # keep (the triple search's extra live values spill there and measured slower)
 ILP_ROWS = 1
 MIX_ILP_ROWS = 2
+MIX_TREE_127 = True
 # nine-branch kernels compile the three cyclic shifts of a permutation type as
 # three row functions, each on the matrix with its columns rotated by s d_p: a
 # type then gathers its input once instead of three times, and its sums need
@@ -412,7 +413,7 @@ def mixed_source(ns, parts, prec, out_dir):
         body_path = os.path.join(out_dir, "%s_c%d_body.inc" % (ns, k))
         with open(body_path, "w") as fh:
             fh.write("// generated: %s, H_o %d x %d, %d edges (code %d of %s)\n" % (name, M, N, int(H.sum()), k, ns))
-            if N > 64:
+            if N > 64 and not MIX_TREE_127:
                 fh.write(body_source_ilp(H, fix8=bool(prec), group=MIX_ILP_ROWS, tree=False))
             else:
                 fh.write(body_source_ilp(H, fix8=bool(prec), group=1, tree=True))
