@@ -71,12 +71,8 @@ MIXES = [
     ([("bch63_36", 122), ("bch63_45", 33), ("bch127_64", 72), ("bch127_99", 33)], 0),
 ]
 # rows whose min searches interleave in the one-wave kernels: one with the
-# triple search (its steps hold two independent triples); two with the
-# entry-by-entry chain that the length-127 codes of the mixed-code kernels
-# keep (the triple search's extra live values spill there and measured slower)
+# triple search (its steps hold two independent triples)
 ILP_ROWS = 1
-MIX_ILP_ROWS = 2
-MIX_TREE_127 = True
 # nine-branch kernels compile the three cyclic shifts of a permutation type as
 # three row functions, each on the matrix with its columns rotated by s d_p: a
 # type then gathers its input once instead of three times, and its sums need
@@ -402,9 +398,8 @@ def body_source_fix8(H: np.ndarray, accumulate: bool = False) -> str:
 def mixed_source(ns, parts, prec, out_dir):
     """Source of one mixed-code kernel: each code's row function and syndrome
     test in a namespace of its own, a traits struct per code, and the
-    template.  parts: [(code name, H, Hstd)].  Length-63 codes take the
-    triple min1/min2 search, length-127 codes the chain of two interleaved
-    rows (see MIX_ILP_ROWS)."""
+    template.  parts: [(code name, H, Hstd)].  Every code takes the triple
+    min1/min2 search of the one-wave kernels."""
     lines = ['#include "mix_launch.h"', "#define SPEC_FIX8 %d" % prec, "#include <hip/hip_runtime.h>",
              "#include <cstdint>", "namespace bch {", "namespace %s {" % ns]
     traits, cases = [], []
@@ -413,10 +408,7 @@ def mixed_source(ns, parts, prec, out_dir):
         body_path = os.path.join(out_dir, "%s_c%d_body.inc" % (ns, k))
         with open(body_path, "w") as fh:
             fh.write("// generated: %s, H_o %d x %d, %d edges (code %d of %s)\n" % (name, M, N, int(H.sum()), k, ns))
-            if N > 64 and not MIX_TREE_127:
-                fh.write(body_source_ilp(H, fix8=bool(prec), group=MIX_ILP_ROWS, tree=False))
-            else:
-                fh.write(body_source_ilp(H, fix8=bool(prec), group=1, tree=True))
+            fh.write(body_source_ilp(H, fix8=bool(prec), group=ILP_ROWS, tree=True))
             fh.write("\n\n" + syndrome_source(Hs) + "\n")
         lines += ["namespace c%d {" % k, '#include "%s"' % os.path.basename(body_path), "}"]
         fn = ("    __device__ static __forceinline__ void body(const float *A, const uint32_t *S, float *T) "
