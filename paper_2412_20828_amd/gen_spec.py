@@ -159,10 +159,14 @@ def fingerprint(H: np.ndarray) -> int:
 # floats order as their bit patterns, so integer min, min3 and med3 give the
 # same values as the float ones, with none of the input canonicalisation the
 # compiler adds around a float min.  med3u is a min/max tree that the compiler
-# matches to one v_med3_u32 in the entry-by-entry chain; med3i is the
-# instruction itself, for the triple search, where the compiler would share a
-# min of the same operands between a triple's least value and its median and
-# split the median into four instructions.
+# matches to one v_med3_u32 in the entry-by-entry chain; med3i, for the triple
+# search, is the float median builtin on the same bit patterns (one
+# v_med3_f32: the magnitudes are canonical non-negative floats, never NaN, and
+# the kernels keep FP32 denormals, so the float and integer medians are the
+# same value).  From the min/max tree the compiler would share a min of the
+# same operands between a triple's least value and its median and split the
+# median into four instructions; written as inline asm it costs a wait state
+# after every use.
 _MED3U = """__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c)
 {
     return min(max(a, b), max(min(a, b), c));
@@ -328,12 +332,13 @@ def body_source_ilp(H: np.ndarray, fix8: bool = False, group: int = 1, tree: boo
     return "\n".join(out)
 
 
-def body_source(H: np.ndarray, accumulate: bool = False) -> str:
+def body_source(H: np.ndarray, accumulate: bool = False, helpers: bool = True) -> str:
     """Row function of the FP32 decoder.  accumulate: add every edge's c2v into
-    T (T holds a running sum over branches) instead of overwriting T."""
+    T (T holds a running sum over branches) instead of overwriting T.
+    helpers: emit the med3 helpers in front (once per source)."""
     M, N = H.shape
-    out = [_MED3U, "__device__ __forceinline__ void body(const float *__restrict__ A, "
-           "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
+    out = ([_MED3U] if helpers else []) + ["__device__ __forceinline__ void body(const float *__restrict__ A, "
+                                           "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
     touched = [False] * N
     for j in range(M):
         cols = [int(c) for c in np.nonzero(H[j])[0]]
@@ -358,7 +363,7 @@ def body_source(H: np.ndarray, accumulate: bool = False) -> str:
     return "\n".join(out)
 
 
-def body_source_fix8(H: np.ndarray, accumulate: bool = False) -> str:
+def body_source_fix8(H: np.ndarray, accumulate: bool = False, helpers: bool = True) -> str:
     """Row function of the fixed-point decoder.  A holds the int8-saturated
     magnitudes (integers 0..127 held exactly as floats).  The c2v magnitude is
     (3m + 2) >> 2 = floor(0.75 m + 0.5) of the row's other-entry minimum m;
@@ -367,8 +372,8 @@ def body_source_fix8(H: np.ndarray, accumulate: bool = False) -> str:
     (A >= min1 + 1 gives a third argument below 0).  All values are small
     integers, so every step is exact."""
     M, N = H.shape
-    out = [_MED3U, "__device__ __forceinline__ void body(const float *__restrict__ A, "
-           "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
+    out = ([_MED3U] if helpers else []) + ["__device__ __forceinline__ void body(const float *__restrict__ A, "
+                                           "const uint32_t *__restrict__ S, float *__restrict__ T)", "{"]
     touched = [False] * N
     for j in range(M):
         cols = [int(c) for c in np.nonzero(H[j])[0]]
@@ -641,7 +646,7 @@ def generate(stage1_lib: str, out_dir: str):
         if variant == 2 and not (group and N > 64):
             raise ValueError("the small-batch variant is for nine branches and N = 127")
         ext = mode == 3
-        # the nine-branch kernels
+        # every nine-branch kernel folds its shifts but the excluded one-wave ones
         fold = FOLD_SHIFTS and regacc and B == 9 and not ext and (
             group or pk16 or (name, rows) not in FOLD_EXCLUDE)
         dp = {63: 21, 127: 42}.get(N, N // 3)
@@ -664,8 +669,8 @@ def generate(stage1_lib: str, out_dir: str):
                                                                 helpers=False)))
                 elif fold:
                     fh.write(_MED3U + "\n" + folded_body_source(
-                        H, dp, lambda Hs: (body_source_fix8(Hs, regacc) if prec else body_source(Hs, regacc))
-                        .replace(_MED3U, "")))
+                        H, dp, lambda Hs: (body_source_fix8(Hs, regacc, helpers=False) if prec
+                                           else body_source(Hs, regacc, helpers=False))))
                 elif regacc and N > 64:
                     fh.write(body_source_ilp(H, fix8=bool(prec), group=ILP_ROWS, tree=True))
                 else:
