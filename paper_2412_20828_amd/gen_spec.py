@@ -520,9 +520,11 @@ def _ext_messages(j, cols, lhs, idx=True, after=None):
 def body_source_pk16(H: np.ndarray, B: int) -> str:
     """Row function of the packed 16-bit fixed-point decoder: A, T hold two
     frames per register (v2s), SL / SH their sign bits.  Adds s_j * mag_j(i)
-    into T[i] for every entry; mag = clamp(100 min1 + q2 - 100 A, q1, q2)
-    with q = (3m + 2) >> 2 (any factor above 96 selects q2 exactly at the
-    argmin, and 100 keeps the product a single packed multiply-add)."""
+    into T[i] for every entry, mag = q1 + (q2 - q1) e with q = (3m + 2) >> 2
+    and e = 1 at an entry equal to min1, 0 elsewhere: the saturating unsigned
+    difference (min1 + 1) - A (one packed instruction; every A is min1 or
+    more).  Ties at min1 have q2 = q1, so every tied entry gets the same
+    magnitude."""
     M, N = H.shape
     colw = H.sum(axis=0)
     if int(colw.max()) * 96 * B > 32767:
@@ -562,16 +564,16 @@ def body_source_pk16(H: np.ndarray, B: int) -> str:
             out.append("        " + " ".join(parts))
         out.append("        const v2s m1 = vmin(x1, y1), m2 = vmin(vmax(x1, y1), vmin(x2, y2));")
         out.append("        const v2s q1 = (m1 * (v2s)3 + (v2s)2) >> (v2s)2, q2 = (m2 * (v2s)3 + (v2s)2) >> (v2s)2;")
-        out.append("        const v2s K = m1 * (v2s)100 + q2;")
-        # the four dependent steps of an entry's update, emitted a group of
+        out.append("        const v2u m1p = __builtin_bit_cast(v2u, m1) + (v2u)1;")
+        out.append("        const v2s sq1 = sg * q1, sdq = sg * (q2 - q1);")
+        # the three dependent steps of an entry's update, emitted a group of
         # entries at a time: a packed 16-bit result read by the next
         # instruction costs a wait state, which independent entries fill
         for g0 in range(0, len(cols), PK16_GROUP):
             grp = cols[g0:g0 + PK16_GROUP]
-            out.append("        " + " ".join("v2s t%d = A[%d] * (v2s)(-100) + K;" % (c, c) for c in grp))
-            out.append("        " + " ".join("t%d = vmin(q2, t%d);" % (c, c) for c in grp))
-            out.append("        " + " ".join("t%d = vmax(q1, t%d);" % (c, c) for c in grp))
-            out.append("        " + " ".join("T[%d] = sg * t%d + T[%d];" % (c, c, c) for c in grp))
+            out.append("        " + " ".join("const v2s e%d = is_min(m1p, A[%d]);" % (c, c) for c in grp))
+            out.append("        " + " ".join("T[%d] = sdq * e%d + T[%d];" % (c, c, c) for c in grp))
+            out.append("        " + " ".join("T[%d] = T[%d] + sq1;" % (c, c) for c in grp))
         out.append("    }")
     out.append("}")
     return "\n".join(out)
