@@ -81,10 +81,10 @@ FIX_SCALE = 4.0
 # and of the generator functions that write its row function); any other build
 # reports traffic null.
 TRAFFIC_B_PER_FRAME = {  # kernel: (fetched, written, family, source hash)
-    "spec_bch127_64_m72_b9": (523.20, 89.44, "one_wave", "0a4d801252c7f5af"),
-    "spec_bch127_99_m33_b9": (522.04, 88.46, "one_wave", "0a4d801252c7f5af"),
-    "spec_bch127_64_m72_b9_fix8_pk16": (135.95, 84.99, "pk16", "39901715f12b16f7"),
-    "spec_bch127_99_m33_b9_fix8_pk16": (135.62, 85.60, "pk16", "39901715f12b16f7"),
+    "spec_bch127_64_m72_b9": (523.11, 90.35, "one_wave", "0a4d801252c7f5af"),
+    "spec_bch127_99_m33_b9": (522.03, 88.35, "one_wave", "0a4d801252c7f5af"),
+    "spec_bch127_64_m72_b9_fix8_pk16": (135.90, 84.46, "pk16", "80d070ec35864e98"),
+    "spec_bch127_99_m33_b9_fix8_pk16": (135.65, 85.67, "pk16", "80d070ec35864e98"),
 }
 KERNEL_FAMILIES = {
     "one_wave": (["csrc/nms_spec_fp32.inc", "csrc/nms_spec_rot.inc", "csrc/nms_spec_cursor.inc"],
