@@ -141,3 +141,28 @@ def test_shift_matrices_fold_a_type_onto_one_gather(N, dp):
             U = _c2v_sums(H, Y)
             direct[(np.arange(N) - s * dp) % N] += U  # entry i of the branch is B[(i - s d_p) mod N]
         np.testing.assert_allclose(folded, direct, rtol=1e-12, atol=1e-12)
+
+
+def test_packed_selection_by_saturating_difference():
+    """The packed row function's c2v magnitude q1 + (q2 - q1) e, with
+    e = (min1 + 1) - A saturated at 0 in unsigned 16 bits, must equal the
+    fixed-point message of the entry, (3 m + 2) >> 2 of the least of the row's
+    other entries (min2 at an entry holding min1, min1 elsewhere), for every
+    min1 <= min2 <= 127 and every entry value the row can hold, ties at min1
+    included."""
+    q = lambda m: (3 * m + 2) >> 2  # noqa: E731
+    for m1 in range(128):
+        for m2 in range(m1, 128):
+            q1, q2 = q(m1), q(m2)
+            for A in [m1] + list(range(m2, 128)):
+                e = max(0, (m1 + 1) - A) & 0xFFFF
+                got = (q1 + ((q2 - q1) * e)) & 0xFFFF
+                other = m2 if A == m1 else m1  # the least of the others
+                assert got == q(other), (m1, m2, A)
+    # the generated row function spends three packed instructions per two
+    # frame-edges on it: the saturating difference, a multiply-add, an add
+    H = np.zeros((2, 63), np.uint8)
+    H[0, [0, 5, 9]] = 1
+    H[1, [1, 5, 20, 40]] = 1
+    src = gen_spec.body_source_pk16(H, 9)
+    assert src.count("is_min(") == 7 and src.count(" + sq1;") == 7
