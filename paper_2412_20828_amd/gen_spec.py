@@ -665,14 +665,13 @@ def generate(stage1_lib: str, out_dir: str):
             elif pk16:
                 fh.write(body_source_pk16(H, B))
             else:
-                if fold and N > 64:
+                if fold:
+                    # the triple search; in the grouped N = 63 kernels its extra
+                    # live values spill some registers, and it still measured
+                    # 8% faster than the chain once the shifts were folded
                     fh.write(_MED3U + "\n" + folded_body_source(
                         H, dp, lambda Hs: body_source_ilp(Hs, fix8=bool(prec), group=ILP_ROWS, tree=True,
                                                                 helpers=False)))
-                elif fold:
-                    fh.write(_MED3U + "\n" + folded_body_source(
-                        H, dp, lambda Hs: (body_source_fix8(Hs, regacc, helpers=False) if prec
-                                           else body_source(Hs, regacc, helpers=False))))
                 elif regacc and N > 64:
                     fh.write(body_source_ilp(H, fix8=bool(prec), group=ILP_ROWS, tree=True))
                 else:
