@@ -444,9 +444,11 @@ def run_serve(args):
     def fresh():
         return [serving.Request(code=d.code, llr=f.llr, rid=k) for k, (d, f) in enumerate(zip(tr, frs))]
 
-    warm = fresh()[:32]
-    for _ in range(args.warmup):
-        serving.run_trace(eng, warm, [0.0] * len(warm))
+    # untimed: each warm-up step is three bursts of the whole trace, which
+    # replay every slot's graph several times (the first replays of a captured
+    # graph, and the first bursts, run slower than the service's steady state)
+    for _ in range(3 * args.warmup):
+        serving.run_trace(eng, fresh(), [0.0] * len(tr))
     serving.settle_gc()
     done, wall = serving.run_trace(eng, fresh(), [0.0] * len(tr))
     sat = serving.summarize(done, wall)

@@ -126,6 +126,15 @@ int bch_make_automorphisms(int N, int n_branches, int d_o, int16_t *maps);
  * frame_base < 0. */
 int bch_draw_offsets(int N, uint64_t seed, uint64_t key_hi, int64_t frame_base, int64_t F, uint8_t *d_o,
                      int on_device, hipStream_t stream);
+/* The same draw for several keys in one host call (a service's batch of
+ * requests, each keyed by its own id): key k's counts[k] frames, uids 0 to
+ * counts[k] - 1, are written to d_o one key after another, so that d_o[o_k + f]
+ * equals bch_draw_offsets(N, seed, keys[k], 0, ...)'s byte f, with o_k the
+ * sum of the counts before k.  keys, counts and d_o are host memory owned by
+ * the caller; BCH_EINVAL for N outside [7, 127], n_keys < 0, a negative
+ * count or a NULL pointer with n_keys > 0. */
+int bch_draw_offsets_keys(int N, uint64_t seed, int64_t n_keys, const uint64_t *keys, const int64_t *counts,
+                          uint8_t *d_o);
 
 /* ------------------------------------------------------------------------
  * Decoder (Algorithm 1 of Section III-B; plain NMS of Section II-A as the

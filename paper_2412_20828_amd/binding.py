@@ -38,7 +38,7 @@ SYMBOLS = [
     "bch_decoder_destroy", "bch_decode_workspace_size", "bch_nms_decode_batch",
     "bch_syndrome_check", "bch_quantize_llr", "bch_osd_decode", "bch_decoder_set_tuning",
     "bch_mixed_workspace_size", "bch_mixed_decode_batch", "bch_osd_decode_device", "bch_mixed_osd_decode",
-    "bch_draw_offsets", "bch_pcm_stats", "bch_nms_decode_batch_noalloc", "bch_mixed_kernel_name",
+    "bch_draw_offsets", "bch_draw_offsets_keys", "bch_pcm_stats", "bch_nms_decode_batch_noalloc", "bch_mixed_kernel_name",
 ]
 MAX_MIX = 8
 
@@ -88,6 +88,7 @@ def lib():
     L.bch_pcm_destroy.restype = None
     L.bch_make_automorphisms.argtypes = [i32, i32, i32, P]
     L.bch_draw_offsets.argtypes = [i32, u64, u64, i64, i64, P, i32, P]
+    L.bch_draw_offsets_keys.argtypes = [i32, u64, i64, P, P, P]
     L.bch_pcm_stats.argtypes = [P, P, P, P, P]
     L.bch_decoder_create.argtypes = [P, P, ctypes.POINTER(DecParams), P]
     L.bch_decoder_is_specialized.argtypes = [P]
@@ -235,6 +236,22 @@ def draw_offsets(N: int, seed: int, key_hi: int, frame_base: int, F: int, out=No
     _check(lib().bch_draw_offsets(N, seed, key_hi, frame_base, F, _dptr(out), 1, _stream(stream)),
            "bch_draw_offsets")
     return out
+
+
+def draw_offsets_keys(N: int, seed: int, keys, counts, out=None):
+    """Offsets of several keys in one host call (bch_draw_offsets_keys): key
+    k's counts[k] frames one key after another.  out: a host uint8 numpy array
+    of sum(counts) contiguous bytes, or None (a new array)."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    counts = np.ascontiguousarray(counts, dtype=np.int64)
+    if keys.shape != counts.shape or keys.ndim != 1:
+        raise BchError("keys and counts must be 1-D and of one length")
+    F = int(counts.sum())
+    d = np.zeros(F, np.uint8) if out is None else out
+    if d.dtype != np.uint8 or d.shape != (F,) or not d.flags.c_contiguous:
+        raise BchError("d_o must be sum(counts) contiguous uint8")
+    _check(lib().bch_draw_offsets_keys(N, seed, keys.size, _np(keys), _np(counts), _np(d)), "bch_draw_offsets_keys")
+    return d
 
 
 class Decoder:

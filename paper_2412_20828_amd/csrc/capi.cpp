@@ -488,6 +488,26 @@ int bch_draw_offsets(int N, uint64_t seed, uint64_t key_hi, int64_t frame_base, 
     return BCH_OK;
 }
 
+int bch_draw_offsets_keys(int N, uint64_t seed, int64_t n_keys, const uint64_t *keys, const int64_t *counts,
+                          uint8_t *d_o)
+{
+    if (N < 7 || N > 127 || n_keys < 0)
+        return fail(BCH_EINVAL, "bad argument (7 <= N <= 127, n_keys >= 0)");
+    if (n_keys == 0)
+        return BCH_OK;
+    if (!keys || !counts || !d_o)
+        return fail(BCH_EINVAL, "NULL argument");
+    for (int64_t k = 0; k < n_keys; k++)
+        if (counts[k] < 0)
+            return fail(BCH_EINVAL, "negative count");
+    const int dp = shift_period(N);
+    int64_t o = 0;
+    for (int64_t k = 0; k < n_keys; k++)
+        for (int64_t f = 0; f < counts[k]; f++)
+            d_o[o++] = draw_offset(seed, keys[k], (uint64_t)f, dp);
+    return BCH_OK;
+}
+
 int bch_decoder_create(bch_code code, bch_pcm pcm, const bch_dec_params *params, bch_decoder *out)
 {
     if (!code || !pcm || !params || !out)

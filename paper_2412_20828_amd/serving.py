@@ -261,6 +261,24 @@ class Engine:
             return B.draw_offsets(N, self.seed, req.rid, 0, req.frames)
         return B.draw_offsets(N, self.seed, req.rid, 0, req.frames, out=out)
 
+    def _draw_segment(self, code: int, rs, hd):
+        """Offsets of the requests rs = [(request, offset in the slot)] of one
+        code in one library call (keys = request ids), written into the
+        slot's offset bytes hd: in place when the requests lie back to back,
+        else through a temporary."""
+        N = self.codes[code][0].N
+        keys = np.fromiter((r.rid for r, _ in rs), np.uint64, len(rs))
+        counts = np.fromiter((r.frames for r, _ in rs), np.int64, len(rs))
+        lo, hi = rs[0][1], rs[-1][1] + rs[-1][0].frames
+        if hi - lo == int(counts.sum()):
+            B.draw_offsets_keys(N, self.seed, keys, counts, out=hd[lo:hi])
+            return
+        d = B.draw_offsets_keys(N, self.seed, keys, counts)
+        o = 0
+        for r, off in rs:
+            hd[off:off + r.frames] = d[o:o + r.frames]
+            o += r.frames
+
     def busy(self) -> bool:
         return bool(self.pending or self.osd_jobs or any(s.busy for s in self.slots))
 
@@ -318,16 +336,20 @@ class Engine:
         hl, hd = s.h_llr.numpy(), s.h_do.numpy()
         now = time.perf_counter()
         s.members = []
+        drawn = [[] for _ in self.decs]  # requests whose offsets the engine draws, per code
         for r in take:
             off, F, w = pos[r.code], r.frames, min(r.llr.shape[1], self.ld)
             hl[off:off + F, :w] = r.llr[:, :w]
             if r.d_o is None:
-                self.draw_offsets(r, hd[off:off + F])
+                drawn[r.code].append((r, off))
             else:
                 hd[off:off + F] = r.d_o
             r.t_admit = now
             s.members.append((r, off))
             pos[r.code] += F
+        for c, rs in enumerate(drawn):
+            if rs:
+                self._draw_segment(c, rs, hd)
         if self.graph and n >= self.graph_min_frames:
             # code bytes of this batch, and 255 over what the slot's previous
             # replay used beyond it, so that the replay decodes exactly these
@@ -383,22 +405,26 @@ class Engine:
         hb = s.h_bits.numpy().view(np.uint64)
         hi, hf = s.h_iters.numpy(), s.h_flags.numpy()
         by_code = {}
+        dev_osd = self.osd_order is not None and self.osd_on == "device"
         for r, off in s.members:
             F = r.frames
-            W = self.decs[r.code].W64
-            r.bits = np.zeros((F, 2), np.uint64)
-            r.bits[:, :W] = hb[off:off + F, :W]
+            if self.decs[r.code].W64 == 2:
+                r.bits = hb[off:off + F].copy()
+            else:
+                # the slot's second word may hold a longer code's bits from
+                # an earlier step
+                r.bits = np.zeros((F, 2), np.uint64)
+                r.bits[:, 0] = hb[off:off + F, 0]
             r.iters = hi[off:off + F].copy()
-            r.flags = hf[off:off + F].copy() & FLAG_CONVERGED
+            r.flags = hf[off:off + F] & FLAG_CONVERGED  # a new array
             r.t_gpu = now
-            failed = np.nonzero(r.flags == 0)[0]
-            r.n_osd = int(failed.size)
-            if r.n_osd and self.osd_order is not None and self.osd_on == "device":
-                r.flags[failed] |= FLAG_OSD  # decided on the device in the same slot
+            r.n_osd = F - int(np.count_nonzero(r.flags))
+            if r.n_osd and dev_osd:
+                r.flags[r.flags == 0] = FLAG_OSD  # decided on the device in the same slot
                 r.t_done = now
                 done.append(r)
             elif r.n_osd and self.osd_pool is not None:
-                by_code.setdefault(r.code, []).append((r, failed))
+                by_code.setdefault(r.code, []).append((r, np.flatnonzero(r.flags == 0)))
             else:
                 r.t_done = now
                 done.append(r)

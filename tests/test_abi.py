@@ -119,6 +119,22 @@ def test_host_offset_draw_matches_oracle(B, N):
         B.draw_offsets(N, 0, 0, -1, 4)
 
 
+@pytest.mark.parametrize("N", [63, 127])
+def test_keyed_offset_draw_matches_the_oracle_per_key(B, N):
+    """One call over several keys equals the oracle's draw of each key's frames
+    from uid 0, key after key (empty keys included)."""
+    rng = np.random.default_rng(N)
+    keys = rng.integers(0, 2 ** 63, 40, dtype=np.uint64)
+    counts = rng.integers(0, 300, 40).astype(np.int64)
+    counts[[3, 17]] = 0
+    got = B.draw_offsets_keys(N, 2 ** 63 + 11, keys, counts)
+    want = np.concatenate([oracle.draw_offsets(N, 2 ** 63 + 11, int(k), 0, int(c)) for k, c in zip(keys, counts)])
+    assert np.array_equal(got, want)
+    assert B.draw_offsets_keys(N, 1, keys[:0], counts[:0]).size == 0
+    with pytest.raises(B.BchError):
+        B.draw_offsets_keys(N, 0, keys[:2], np.array([4, -1], np.int64), out=np.zeros(3, np.uint8))
+
+
 def test_synth_offsets_follow_the_library_draw(B):
     fr = synth.frames("bch63_36", 500, 3.0, seed=12, block=4)
     assert np.array_equal(fr.d_o, B.draw_offsets(63, 12, synth.offset_key("bch63_36", 4), 0, 500))
