@@ -459,15 +459,14 @@ def run_serve(args):
     fer_n = np.mean(np.concatenate([((r.flags & serving.FLAG_OSD) != 0) | (r.bits != pack(truth[r.rid])).any(1)
                                     for r in done]))
     osd_cost = osd_costs(eng, done, torch)
-    # untimed: a paced warm-up at the lowest offered load takes the small-step
-    # (code by code) paths once before they are timed, then the setup's objects
-    # leave the collector's working set (serving.settle_gc)
-    pace = SERVE_LOADS[0] * sat["frames_per_s"] / mean_frames
-    serving.run_trace(eng, fresh()[:256], [d.t / pace for d in tr[:256]])
     serving.settle_gc()
     loads = []
     for frac in SERVE_LOADS:
         rate = frac * sat["frames_per_s"] / mean_frames
+        # untimed: the first 256 requests at this load, so that the timed
+        # trace starts from the service's steady state at that load (after a
+        # burst or an idle gap the first steps take longer)
+        serving.run_trace(eng, fresh()[:256], [d.t / rate for d in tr[:256]])
         done, wall = serving.run_trace(eng, fresh(), [d.t / rate for d in tr])
         row = serving.summarize(done, wall)
         row.update({"offered_fraction": frac, "offered_frames_per_s": rate * mean_frames,

@@ -122,6 +122,8 @@ class _Slot:
     ws_mix: object = None   # graph mode: workspace of the mixed call
     graph: object = None    # graph mode: the slot's captured decode + OSD
     prev_n: int = 0         # frames of the slot's previous batch (their code bytes are reset)
+    n: int = 0              # frames of the batch in flight
+    segs: list = field(default_factory=list)      # (first frame, frames) of each code in it
     members: list = field(default_factory=list)   # (request, offset)
     busy: bool = False
 
@@ -174,6 +176,11 @@ class Engine:
         self.osd_threads = osd_threads
         self.pending = collections.deque()
         self.osd_pool = ThreadPoolExecutor(1) if osd_order is not None and osd_on == "host" else None
+        # staging of a step's frames (LLR copies into the pinned buffer and the
+        # offset draws), one task per code: numpy's large copies and the
+        # library's draw release the interpreter lock, so the codes' parts run
+        # side by side instead of on the scheduler thread alone
+        self.stage_pool = ThreadPoolExecutor(len(codes))
         self.osd_jobs = []
         ws_bytes = [max(1, m.workspace_size(slot_frames)) for m in self.mixes1]
         self.slots = []
@@ -261,6 +268,20 @@ class Engine:
             return B.draw_offsets(N, self.seed, req.rid, 0, req.frames)
         return B.draw_offsets(N, self.seed, req.rid, 0, req.frames, out=out)
 
+    def _stage(self, code: int, rs, hl, hd):
+        """LLRs and offsets of the requests rs = [(request, offset in the
+        slot)] of one code into the slot's pinned staging buffers."""
+        drawn = []
+        for r, off in rs:
+            F, w = r.frames, min(r.llr.shape[1], self.ld)
+            hl[off:off + F, :w] = r.llr[:, :w]
+            if r.d_o is None:
+                drawn.append((r, off))
+            else:
+                hd[off:off + F] = r.d_o
+        if drawn:
+            self._draw_segment(code, drawn, hd)
+
     def _draw_segment(self, code: int, rs, hd):
         """Offsets of the requests rs = [(request, offset in the slot)] of one
         code in one library call (keys = request ids), written into the
@@ -336,20 +357,17 @@ class Engine:
         hl, hd = s.h_llr.numpy(), s.h_do.numpy()
         now = time.perf_counter()
         s.members = []
-        drawn = [[] for _ in self.decs]  # requests whose offsets the engine draws, per code
+        per_code = [[] for _ in self.decs]
         for r in take:
-            off, F, w = pos[r.code], r.frames, min(r.llr.shape[1], self.ld)
-            hl[off:off + F, :w] = r.llr[:, :w]
-            if r.d_o is None:
-                drawn[r.code].append((r, off))
-            else:
-                hd[off:off + F] = r.d_o
+            off = pos[r.code]
             r.t_admit = now
             s.members.append((r, off))
-            pos[r.code] += F
-        for c, rs in enumerate(drawn):
-            if rs:
-                self._draw_segment(c, rs, hd)
+            per_code[r.code].append((r, off))
+            pos[r.code] += r.frames
+        s.n, s.segs = n, list(zip(start, counts))
+        futs = [self.stage_pool.submit(self._stage, c, rs, hl, hd) for c, rs in enumerate(per_code) if rs]
+        for f in futs:
+            f.result()
         if self.graph and n >= self.graph_min_frames:
             # code bytes of this batch, and 255 over what the slot's previous
             # replay used beyond it, so that the replay decodes exactly these
@@ -402,28 +420,26 @@ class Engine:
     def _finish_slot(self, s: _Slot):
         done = []
         now = time.perf_counter()
-        hb = s.h_bits.numpy().view(np.uint64)
-        hi, hf = s.h_iters.numpy(), s.h_flags.numpy()
-        by_code = {}
+        n = s.n
+        # one copy of the batch's outputs; the requests get views of it
+        bits = s.h_bits.numpy().view(np.uint64)[:n].copy()
+        iters = s.h_iters.numpy()[:n].copy()
+        flags = s.h_flags.numpy()[:n] & FLAG_CONVERGED
+        for c, (st, cnt) in enumerate(s.segs):
+            if cnt and self.decs[c].W64 == 1:
+                bits[st:st + cnt, 1] = 0  # may hold a longer code's bits from an earlier batch
+        conv = np.zeros(n + 1, np.int64)
+        np.cumsum(flags, out=conv[1:])
         dev_osd = self.osd_order is not None and self.osd_on == "device"
+        if dev_osd:
+            flags[flags == 0] = FLAG_OSD  # decided on the device in the same slot
+        by_code = {}
         for r, off in s.members:
             F = r.frames
-            if self.decs[r.code].W64 == 2:
-                r.bits = hb[off:off + F].copy()
-            else:
-                # the slot's second word may hold a longer code's bits from
-                # an earlier step
-                r.bits = np.zeros((F, 2), np.uint64)
-                r.bits[:, 0] = hb[off:off + F, 0]
-            r.iters = hi[off:off + F].copy()
-            r.flags = hf[off:off + F] & FLAG_CONVERGED  # a new array
+            r.bits, r.iters, r.flags = bits[off:off + F], iters[off:off + F], flags[off:off + F]
             r.t_gpu = now
-            r.n_osd = F - int(np.count_nonzero(r.flags))
-            if r.n_osd and dev_osd:
-                r.flags[r.flags == 0] = FLAG_OSD  # decided on the device in the same slot
-                r.t_done = now
-                done.append(r)
-            elif r.n_osd and self.osd_pool is not None:
+            r.n_osd = F - int(conv[off + F] - conv[off])
+            if r.n_osd and not dev_osd and self.osd_pool is not None:
                 by_code.setdefault(r.code, []).append((r, np.flatnonzero(r.flags == 0)))
             else:
                 r.t_done = now
@@ -452,6 +468,7 @@ class Engine:
     def close(self):
         if self.osd_pool is not None:
             self.osd_pool.shutdown(wait=True)
+        self.stage_pool.shutdown(wait=True)
 
 
 def decode_alone(engine: Engine, req: Request):
