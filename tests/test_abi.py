@@ -152,3 +152,26 @@ def test_pcm_stats_match_oracle(B, name):
             assert tuple(got[k]) == tuple(want[k])
         for k in ("col_mean", "col_std", "row_mean", "row_std"):
             assert abs(got[k] - want[k]) < 1e-12
+
+
+def test_engine_draw_segment_equals_per_request_draws(B):
+    """The serving engine's per-code draw (one keyed library call) writes each
+    request's offsets where the per-request draw would, both for requests that
+    lie back to back and for requests with caller-given offsets between them."""
+    import types
+
+    from paper_2412_20828_amd import serving
+    eng = types.SimpleNamespace(codes=[(types.SimpleNamespace(N=127), None)], seed=31)
+    sizes = [5, 300, 1, 77, 64]
+    reqs = [types.SimpleNamespace(rid=1000 + k, frames=F) for k, F in enumerate(sizes)]
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    hd = np.full(sum(sizes), 0xff, np.uint8)
+    serving.Engine._draw_segment(eng, 0, list(zip(reqs, offs)), hd)  # back to back: in place
+    want = np.concatenate([B.draw_offsets(127, 31, r.rid, 0, r.frames) for r in reqs])
+    assert np.array_equal(hd, want)
+    hd[:] = 0xff
+    gap = [(r, o) for k, (r, o) in enumerate(zip(reqs, offs)) if k != 2]  # request 2 brings its own
+    serving.Engine._draw_segment(eng, 0, gap, hd)
+    for r, o in gap:
+        assert np.array_equal(hd[o:o + r.frames], B.draw_offsets(127, 31, r.rid, 0, r.frames))
+    assert (hd[offs[2]:offs[2] + sizes[2]] == 0xff).all()
