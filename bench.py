@@ -31,6 +31,7 @@ frames (Wilson 95% intervals) and its throughput on the host's cores.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -467,7 +468,13 @@ def run_serve(args):
         # trace starts from the service's steady state at that load (after a
         # burst or an idle gap the first steps take longer)
         serving.run_trace(eng, fresh()[:256], [d.t / rate for d in tr[:256]])
-        done, wall = serving.run_trace(eng, fresh(), [d.t / rate for d in tr])
+        reqs = fresh()
+        gc.collect()
+        gc.disable()  # no collection inside the timed trace; one after it
+        try:
+            done, wall = serving.run_trace(eng, reqs, [d.t / rate for d in tr])
+        finally:
+            gc.enable()
         row = serving.summarize(done, wall)
         row.update({"offered_fraction": frac, "offered_frames_per_s": rate * mean_frames,
                     "offered_requests_per_s": rate})
